@@ -1,0 +1,105 @@
+/*
+ * Plain FP64 CPU oracle of the Late Adjusted Parallel Sampler (LAPS),
+ * Robnik & Seljak, "Faster parallel MCMC: Metropolis adjustment is best
+ * served warm" (arXiv 2601.16696).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * code with the GPU library: no headers, no helpers, no constant tables.
+ *
+ * Every function is single-threaded plain loops in double precision.
+ * Ensemble sums run in chain order with Neumaier compensation; all
+ * ensemble averages divide by M (the number of chains).
+ *
+ * Parity pins: see the test files under tests/ (oracle pins) -- each
+ * function below names the passage of the paper it follows.
+ */
+#ifndef LAPS_ORACLE_H
+#define LAPS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- counter-based random numbers (Philox4x64-10, Salmon et al. SC'11) ---- */
+enum { ORC_TAG_O_FIRST = 1, ORC_TAG_O_SECOND = 2, ORC_TAG_FULL_REFRESH = 3,
+       ORC_TAG_MH = 4, ORC_TAG_INIT_DIR = 5 };
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+double orc_u01(uint64_t w);
+/* d standard normals for (chain, step t, tag, substep). */
+void orc_normals(uint64_t seed, uint64_t chain, uint64_t t, uint32_t tag,
+                 uint32_t substep, int64_t d, double *z);
+double orc_mh_uniform(uint64_t seed, uint64_t chain, uint64_t t);
+
+/* ---- targets (log p up to an additive constant, and its gradient) ---- */
+enum { ORC_GAUSS_DIAG = 0, ORC_LOGREG = 1, ORC_STOCHVOL = 2, ORC_PHI4 = 3 };
+typedef struct {
+  int32_t kind;
+  int64_t d;
+  const double *a;  /* gauss: sigma^2 [d]; logreg: X [n][d]; stochvol: y [T] */
+  const double *b;  /* logreg: labels [n] in {0,1} */
+  int64_t n;        /* logreg: n data rows; stochvol: T; phi4: side L */
+  double p0, p1;    /* phi4: m^2, lambda */
+} orc_target;
+
+double orc_logp_grad(const orc_target *tg, const double *x, double *g);
+
+/* ---- single-chain maps of the integrator (Appendix D) ---- */
+void orc_map_O(double *u, const double *z, int64_t d, double h, double L);
+double orc_map_B(double *u, const double *gt, int64_t d, double h);
+void orc_map_A(double *x, const double *u, const double *sigma, int64_t d, double h);
+
+/* coefficient sets: 0 = LF, 1 = MN2, 2 = MN4 */
+int orc_integrator_coeffs(int which, double *b, double *a, int *K);
+
+/* ---- ensemble sampler ---- */
+typedef struct {
+  int64_t n_chains, d;
+  uint64_t seed;
+  double C, alpha, eps0_factor, switch_tol, window_frac, acc_tol, acc_target, L_partial_factor;
+  int32_t n_steps_traj, integrator_adj, eevpd_mode, switch_policy;
+  int64_t max_steps_unadj, max_steps_total;
+} orc_config;
+
+typedef struct orc_ctx orc_ctx;
+
+orc_ctx *orc_create(const orc_config *cfg, const orc_target *tg);
+void orc_destroy(orc_ctx *c);
+/* x0: [N][d]; u0 may be NULL (then u = g/|g|). */
+int orc_init(orc_ctx *c, const double *x0, const double *u0);
+/* moves every chain one unadjusted step with the current eps, L (no controller) */
+void orc_unadj_move(orc_ctx *c);
+/* ensemble statistics + unadjusted controller (eps, L, window, switch) */
+void orc_unadj_control(orc_ctx *c);
+int orc_step_unadjusted(orc_ctx *c, int64_t n);
+void orc_do_switch(orc_ctx *c);
+void orc_mams_move(orc_ctx *c);
+void orc_adj_control(orc_ctx *c);
+int orc_step_adjusted(orc_ctx *c, int64_t n);
+int orc_run(orc_ctx *c);
+
+/* accessors (arrays are owned by the context) */
+typedef struct {
+  int64_t t, grads_per_chain;
+  int32_t phase, adapt, switch_ready, status_bits;
+  double eps, L, eevpd, eevpd_target, dtilde, max_delta, acc_mean;
+  int64_t n_nonfinite;
+  int32_t integrator, have_lo, have_hi, ring_full;
+  double lo, hi, a_star, sum_var;
+} orc_stats;
+void orc_get_stats(const orc_ctx *c, orc_stats *s);
+double *orc_ptr(orc_ctx *c, int which);
+void orc_set_hyper(orc_ctx *c, double eps, double L);
+
+/* closed forms used by the controller */
+double orc_F(double D);
+
+/* neumaier-compensated sum of n doubles */
+double orc_sum(const double *v, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
