@@ -52,20 +52,25 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 /* 53 high bits, offset by half a unit: the result lies in (0, 1]. */
 double orc_u01(uint64_t w) { return ((double)(w >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
 
-/* d standard normals by the Box-Muller transform (Box & Muller 1958): the
- * Philox block j fills z[4j .. 4j+3] from its words (w0,w1) and (w2,w3). */
+/* a 32-bit word offset by half a unit: exactly representable, in (0, 1). */
+static double u01_32(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+/* d standard normals by the Box-Muller transform (Box & Muller 1958).  Philox
+ * block j fills z[8j .. 8j+7]: word k gives the pair (U_a, U_b) from its high
+ * and low 32 bits, z[8j+2k] = r cos(2 pi U_b), z[8j+2k+1] = r sin(2 pi U_b),
+ * r = sqrt(-2 ln U_a). */
 void orc_normals(uint64_t seed, uint64_t chain, uint64_t t, uint32_t tag,
                  uint32_t substep, int64_t d, double *z) {
   const uint64_t key[2] = {seed, 0};
-  for (int64_t j = 0; 4 * j < d; ++j) {
+  for (int64_t j = 0; 8 * j < d; ++j) {
     uint64_t ctr[4] = {chain, (uint64_t)j, t, (uint64_t)tag | ((uint64_t)substep << 8)};
     uint64_t w[4];
     orc_philox4x64_10(ctr, key, w);
-    for (int p = 0; p < 2; ++p) {
-      double ua = orc_u01(w[2 * p]), ub = orc_u01(w[2 * p + 1]);
+    for (int k = 0; k < 4; ++k) {
+      double ua = u01_32((uint32_t)(w[k] >> 32)), ub = u01_32((uint32_t)w[k]);
       double r = sqrt(-2.0 * log(ua));
       double ang = 2.0 * M_PI * ub;
-      int64_t i0 = 4 * j + 2 * p;
+      int64_t i0 = 8 * j + 2 * k;
       if (i0 < d) z[i0] = r * cos(ang);
       if (i0 + 1 < d) z[i0 + 1] = r * sin(ang);
     }
@@ -309,7 +314,7 @@ orc_ctx *orc_create(const orc_config *cfg, const orc_target *tg) {
   c->Tw = (int64_t)llround(cfg->window_frac * (double)cfg->max_steps_total);
   if (c->Tw < 2) c->Tw = 2;
   c->ring = alloc0(c->Tw * d);
-  c->x0 = alloc0(d); c->g0 = alloc0(d); c->tmp = alloc0(d); c->z = alloc0(d + 4);
+  c->x0 = alloc0(d); c->g0 = alloc0(d); c->tmp = alloc0(d); c->z = alloc0(d + 8);
   return c;
 }
 

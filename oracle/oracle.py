@@ -124,7 +124,7 @@ def u01(w: int) -> float:
 
 
 def normals(seed, chain, t, tag, substep, d) -> np.ndarray:
-    z = np.zeros(d + 4)
+    z = np.zeros(d + 8)
     lib().orc_normals(seed, chain, t, tag, substep, d, _p(z))
     return z[:d].copy()
 

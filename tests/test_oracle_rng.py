@@ -66,19 +66,22 @@ def test_normals_streams_are_distinct_and_reproducible(orc):
     for other in (b, c, d, e):
         assert not np.allclose(a, other)
     assert np.array_equal(a, orc.normals(1, 0, 0, 1, 0, 64))
-    # a prefix of a longer request is the shorter request (blocks are per 4 dims)
+    # a prefix of a longer request is the shorter request (blocks are per 8 dims)
     assert np.array_equal(orc.normals(1, 0, 0, 1, 0, 10), a[:10])
 
 
 def test_normals_block_layout(orc):
-    # block j of the stream fills dims 4j..4j+3 by Box-Muller on its words (w0,w1),(w2,w3)
-    w = orc.philox4x64_10([5, 2, 9, 1 | (3 << 8)], [77, 0])
-    u = [orc.u01(int(v)) for v in w]
-    r0, r1 = np.sqrt(-2 * np.log(u[0])), np.sqrt(-2 * np.log(u[2]))
-    ref = [r0 * np.cos(2 * np.pi * u[1]), r0 * np.sin(2 * np.pi * u[1]),
-           r1 * np.cos(2 * np.pi * u[3]), r1 * np.sin(2 * np.pi * u[3])]
-    z = orc.normals(77, 5, 9, 1, 3, 12)
-    np.testing.assert_allclose(z[8:12], ref, rtol=1e-15, atol=1e-15)
+    # block j of the stream fills dims 8j..8j+7; word k gives (U_a, U_b) from its
+    # high and low halves, (w + 1/2) / 2^32, and Box-Muller makes the pair
+    w = orc.philox4x64_10([5, 1, 9, 1 | (3 << 8)], [77, 0])
+    ref = []
+    for v in w:
+        ua = ((int(v) >> 32) + 0.5) / 2.0**32
+        ub = ((int(v) & 0xFFFFFFFF) + 0.5) / 2.0**32
+        r = np.sqrt(-2 * np.log(ua))
+        ref += [r * np.cos(2 * np.pi * ub), r * np.sin(2 * np.pi * ub)]
+    z = orc.normals(77, 5, 9, 1, 3, 20)
+    np.testing.assert_allclose(z[8:16], ref, rtol=1e-15, atol=1e-15)
 
 
 def test_mh_uniform_stream(orc):
