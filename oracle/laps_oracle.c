@@ -241,6 +241,17 @@ double orc_map_B(double *u, const double *gt, int64_t d, double h) {
   const double delta = h * n / (double)(d - 1);
   double c = 0.0;
   for (int64_t i = 0; i < d; ++i) c += (gt[i] / n) * u[i];
+  if (fabs(delta) >= 20.0) {
+    /* the same quotient divided through by cosh(delta): sech u + (tanh + c(1 - sech)) e
+     * over 1 + c tanh, and log cosh = |delta| + log(1 + e^{-2|delta|}) - ln 2; cosh and
+     * sinh themselves overflow beyond |delta| ~ 710 */
+    const double ad = fabs(delta), e2 = exp(-2.0 * ad);
+    const double tau = copysign((1.0 - e2) / (1.0 + e2), delta);
+    const double sech = 2.0 * exp(-ad) / (1.0 + e2);
+    const double Dh = 1.0 + c * tau;
+    for (int64_t i = 0; i < d; ++i) u[i] = (sech * u[i] + (tau + c * (1.0 - sech)) * (gt[i] / n)) / Dh;
+    return (double)(d - 1) * (ad + log1p(e2) - M_LN2 + log(Dh));
+  }
   const double sh = sinh(delta);
   const double shh = sinh(0.5 * delta);
   const double chm1 = 2.0 * shh * shh;

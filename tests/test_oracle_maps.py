@@ -206,3 +206,41 @@ def test_composition_energy_error_order(orc, which, order):
         errs.append(abs(E))
     slopes = np.diff(np.log(errs)) / np.diff(np.log(epss))
     assert np.all(np.abs(slopes - order) < 0.35), slopes
+
+
+@pytest.mark.parametrize("d,h,gscale,cmix", [(3, 0.05, 1500.0, 0.3), (10, 2.0, 400.0, -0.6), (4, 0.9, 3000.0, 0.9),
+                                             (50, 0.4, 2600.0, 0.0), (5, 0.012, 7000.0, -0.2)])
+def test_B_large_delta_against_multiprecision(orc, d, h, gscale, cmix):
+    """|delta| from about 20 to beyond cosh overflow: the oracle matches the
+    paper's closed form evaluated in 60-digit arithmetic."""
+    import mpmath as mp
+    mp.mp.dps = 60
+    rng = np.random.default_rng(d)
+    g = gscale * _unit(rng.normal(size=d))
+    w = rng.normal(size=d)
+    w -= g * (w @ g) / (g @ g)
+    u = cmix * g / np.linalg.norm(g) + np.sqrt(1 - cmix**2) * _unit(w)
+    u1, dk = orc.map_B(u, g, h)
+    n = mp.sqrt(mp.fsum(mp.mpf(v) ** 2 for v in g))
+    delta = mp.mpf(h) * n / (d - 1)
+    assert float(delta) > 19.0
+    c = mp.fsum(mp.mpf(a) * mp.mpf(b) for a, b in zip(g, u)) / n
+    den = mp.cosh(delta) + c * mp.sinh(delta)
+    coef = mp.sinh(delta) + c * (mp.cosh(delta) - 1)
+    ref = [float((mp.mpf(u[i]) + coef * mp.mpf(g[i]) / n) / den) for i in range(d)]
+    np.testing.assert_allclose(u1, ref, rtol=0, atol=1e-12)
+    kref = float((d - 1) * mp.log(den))
+    assert abs(dk - kref) < 1e-12 * abs(kref)
+
+
+def test_B_branch_continuity(orc):
+    # the direct form below |delta| = 20 and the cosh-divided form above agree across the switch
+    d = 6
+    g = np.array([3.0, -1.0, 2.0, 0.5, 0.0, 1.0]) * 20.0
+    u = _unit(np.array([0.2, 1.0, -0.3, 0.0, 0.4, 0.1]))
+    n = np.linalg.norm(g)
+    h0 = 20.0 * (d - 1) / n
+    ua, ka = orc.map_B(u, g, h0 * (1 - 1e-12))
+    ub, kb = orc.map_B(u, g, h0 * (1 + 1e-12))
+    np.testing.assert_allclose(ua, ub, atol=1e-10)
+    assert abs(ka - kb) < 1e-9 * abs(ka)
