@@ -1,0 +1,213 @@
+/*
+ * laps.h -- C ABI of the MI355X (gfx950) hot path of the Late Adjusted
+ * Parallel Sampler (LAPS), Robnik & Seljak, "Faster parallel MCMC: Metropolis
+ * adjustment is best served warm", arXiv 2601.16696.
+ *
+ * One ensemble of N chains in d dimensions is advanced on one GPU.  Every
+ * operation of the method runs in HIP kernels of this library; the host only
+ * validates arguments and enqueues work on the caller's stream.
+ *
+ * Memory and ownership
+ *   - All device buffers belong to the caller: the positions x, the
+ *     workspace and the target's data.  The library never allocates device
+ *     memory.  It owns only the opaque host context (laps_ctx).
+ *   - Positions are row-major [N][ld] in the state precision (double for
+ *     LAPS_F64, float otherwise) with row stride ld = laps_row_stride(d)
+ *     elements (d rounded up to a multiple of 8).  Columns d..ld-1 are padding:
+ *     the library overwrites them with zeros.  Base pointers must be 32-byte
+ *     aligned.
+ *   - x is updated in place by every step.
+ *
+ * Streams and synchronisation
+ *   - Every call enqueues on the stream given to laps_init (a hipStream_t
+ *     passed as void*; NULL is the default stream) and returns without
+ *     waiting, except laps_ensemble_stats, which synchronises that stream.
+ *   - Calls on one context must not overlap from several host threads.
+ *
+ * Errors
+ *   - Every entry point validates its arguments before it enqueues anything
+ *     and returns LAPS_EINVAL (or LAPS_EWORKSPACE, LAPS_EUNSUPPORTED) without
+ *     side effects.  A failed HIP launch returns LAPS_EDEVICE and
+ *     laps_last_error() gives the HIP message.  The library never aborts.
+ *   - Chains whose energy error is not finite are counted; laps_ensemble_stats
+ *     returns LAPS_ENONFINITE (after filling the output) when any were seen.
+ */
+#ifndef LAPS_H
+#define LAPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct laps_ctx laps_ctx;
+
+typedef enum {
+  LAPS_OK = 0,
+  LAPS_EINVAL = -1,
+  LAPS_EDEVICE = -2,
+  LAPS_ENONFINITE = -3,
+  LAPS_EPHASE = -4,
+  LAPS_EWORKSPACE = -5,
+  LAPS_EUNSUPPORTED = -6
+} laps_status;
+
+/* State precision.  LAPS_F64: everything in double.  LAPS_F32: state x, u, g
+ * in float; log p, energy errors and every ensemble reduction in double.
+ * LAPS_MIXED_BF16: as LAPS_F32, and the logistic-regression gradient runs its
+ * two contractions on bf16 matrix cores with float accumulation. */
+typedef enum { LAPS_F64 = 0, LAPS_F32 = 1, LAPS_MIXED_BF16 = 2 } laps_precision;
+
+/* Built-in targets (log p up to a constant):
+ *   LAPS_GAUSS_DIAG  N(0, diag(s2)).            data[0] = s2 [d] (double)
+ *   LAPS_LOGREG      Bayesian logistic regression, prior N(0, I):
+ *                    log p = sum_n [y_n z_n - log(1 + e^{z_n})] - |th|^2/2,
+ *                    z = X th.                   data[0] = X [n][d] row-major
+ *                    (double for LAPS_F64, bf16 bits as uint16 otherwise),
+ *                    data[1] = y [n] (double, 0/1), dims[0] = n
+ *   LAPS_STOCHVOL    stochastic volatility, th = (h_1..h_T, s, r), d = T + 2:
+ *                    sigma = e^s, phi = tanh r, s ~ N(-2, 0.5^2),
+ *                    r ~ N(2, 0.5^2), h_1 ~ N(0, sigma^2/(1-phi^2)),
+ *                    h_t ~ N(phi h_{t-1}, sigma^2), y_t ~ N(0, e^{h_t}).
+ *                                                data[0] = y [T] (double)
+ *   LAPS_PHI4        periodic L x L lattice phi^4, d = L^2, site (r, c) at
+ *                    r*L + c: log p = -sum_x [1/2 sum_mu (phi_{x+mu} - phi_x)^2
+ *                    + m2/2 phi_x^2 + lambda phi_x^4].
+ *                                                dims[0] = L, scal[0] = m2,
+ *                                                scal[1] = lambda
+ * Target data must stay valid and unchanged while a context uses it. */
+typedef enum { LAPS_GAUSS_DIAG = 0, LAPS_LOGREG = 1, LAPS_STOCHVOL = 2, LAPS_PHI4 = 3 } laps_target_kind;
+
+typedef struct {
+  int32_t kind; /* laps_target_kind */
+  int64_t d;
+  const void *data[4];
+  int64_t dims[4];
+  double scal[4];
+} laps_target;
+
+/* Sampler configuration.  Zero-initialise and call laps_config_default() to
+ * get the paper's constants:
+ *   C = 0.025            ratio of asymptotic to current bias (section "Step size")
+ *   alpha = 2            L = alpha (sum_i Var x_i)^{1/2} (eq. L)
+ *   eps0_factor = 0.01   eps_0 = 0.01 sqrt(d) (Algorithm "LAPS Pseudocode")
+ *   switch_tol = 0.01    switch when every windowed fluctuation of E[x_i^2] is
+ *                        below this (section "Switch to adjustment")
+ *   window_frac = 0.2    window length as a fraction of max_steps_total
+ *   acc_tol = 0.03       acceptance tolerance of the adjusted-phase bisection
+ *   acc_target = 0       0: 0.7 for the second-order integrator, 0.9 for MN4
+ *   L_partial_factor = 1.25, n_steps_traj = 15  (section "Adjusted sampling")
+ *   integrator_adj = 0   0: MN2 for d <= 200 else MN4; 1: MN2; 2: MN4
+ *   eevpd_mode = 1       0: Var[Delta]/d (the text's definition); 1: mean of
+ *                        Delta^2 / d (the algorithm's form, default)
+ *   switch_policy = 0    0: the paper's fluctuation rule (or max_steps_unadj);
+ *                        1: switch exactly at max_steps_unadj
+ * Step counts t count integrator steps: one per unadjusted step and
+ * n_steps_traj per adjusted transition. */
+typedef struct {
+  int64_t n_chains, d;
+  int32_t prec; /* laps_precision */
+  uint64_t seed;
+  double C, alpha, eps0_factor, switch_tol, window_frac, acc_tol, acc_target, L_partial_factor;
+  int32_t n_steps_traj, integrator_adj, eevpd_mode, switch_policy;
+  int64_t max_steps_unadj, max_steps_total;
+} laps_config;
+
+/* Snapshot of the device-resident hyperparameters and diagnostics.
+ * phase: 0 unadjusted, 1 unadjusted phase finished (switch pending),
+ * 2 adjusted.  status_bits: 1 non-finite energy error seen, 2 eps update
+ * skipped (EEVPD zero or not finite), 4 a zero or non-finite variance was
+ * replaced by 1 in the preconditioner. */
+typedef struct {
+  int64_t t, grads_per_chain;
+  int32_t phase, adapt, switch_ready, status_bits;
+  double eps, L, eevpd, eevpd_target, dtilde, max_delta, acc_mean;
+  int64_t n_nonfinite;
+  int32_t integrator, have_lo, have_hi, ring_full;
+  double lo, hi, a_star, sum_var;
+} laps_stats;
+
+/* Fills cfg with the paper's defaults for n_chains x d (seed 0,
+ * max_steps_unadj 1000, max_steps_total 2000, precision LAPS_F64). */
+void laps_config_default(laps_config *cfg, int64_t n_chains, int64_t d);
+
+/* Row stride (elements) of every [N][ld] buffer: d rounded up to 8. */
+int64_t laps_row_stride(int64_t d);
+
+/* Device workspace bytes the context needs for (cfg, target). */
+laps_status laps_workspace_size(const laps_config *cfg, const laps_target *target, size_t *bytes);
+
+/* Creates a context, validates everything, and enqueues initialisation
+ * (Algorithm "LAPS Pseudocode" and section "Initialization"): log p and its
+ * gradient at x, u = grad/|grad| (or u0 when given; a uniform random direction
+ * for a chain whose gradient vanishes), eps = eps0_factor sqrt(d),
+ * L = alpha (sum_i Var x_i)^{1/2}.
+ *   x_dev  [N][ld] positions, caller-owned, updated in place by every step
+ *   u0_dev [N][ld] initial velocities (unit norm) or NULL
+ *   ws_dev workspace of at least laps_workspace_size bytes, 256-byte aligned
+ *   stream hipStream_t (as void*) all work is enqueued on
+ * On success *out receives the context; release it with laps_destroy. */
+laps_status laps_init(const laps_config *cfg, const laps_target *target, void *x_dev, const void *u0_dev,
+                      void *ws_dev, size_t ws_bytes, void *stream, laps_ctx **out);
+
+/* Enqueues up to n_steps unadjusted MCLMC steps (eq. discrete update with the
+ * leapfrog integrator, Appendix D) each followed by the ensemble statistics
+ * and the unadjusted controller (section "Unadjusted initialization", eq.
+ * bias bound, eq. L, eq. relative fluctuations).  Once the switch condition
+ * fires on the device the remaining steps are no-ops.  Returns LAPS_EPHASE
+ * after laps_step_adjusted has been called.  Never synchronises. */
+laps_status laps_step_unadjusted(laps_ctx *ctx, int64_t n_steps);
+
+/* Enqueues n_transitions MAMS transitions (Appendix "Metropolis adjusted
+ * microcanonical dynamics") each followed by the acceptance-rate bisection
+ * controller (section "Adjusted sampling").  The first call performs the
+ * switch: diagonal preconditioner sigma_i = Var[x_i]^{1/2}, integrator MN2
+ * (d <= 200) or MN4, target acceptance 0.7 or 0.9.  Transitions starting at
+ * t >= max_steps_total are no-ops.  Never synchronises. */
+laps_status laps_step_adjusted(laps_ctx *ctx, int64_t n_transitions);
+
+/* Synchronises the stream and copies the hyperparameters/diagnostics to
+ * out_host.  per_dim_dev, if not NULL, receives [4][d] doubles on the device:
+ * mean, variance, E[x_i^2] and the equipartition diagonal V_ii of the last
+ * statistics pass. */
+laps_status laps_ensemble_stats(laps_ctx *ctx, laps_stats *out_host, double *per_dim_dev);
+
+/* Standalone target evaluation for n_chains rows of x ([n][ld] in the
+ * precision's state type): logp_dev [n] doubles, grad_dev [n][ld] (may be
+ * NULL).  Enqueued on stream; used by the autograd wrappers. */
+laps_status laps_target_eval(const laps_target *target, int32_t prec, const void *x_dev, void *logp_dev,
+                             void *grad_dev, int64_t n_chains, void *stream);
+
+/* The sampler's random-number contract, exposed for reproduction and tests.
+ * Philox4x64-10 (Salmon et al., SC'11) under key (seed, 0):
+ *   laps_philox_words: ctr_dev [n][4] uint64 counters -> out_dev [n][4]
+ *   uint64 words (device buffers, enqueued on stream).
+ * The sampler's normals for (chain m, step t, tag, substep) use counter
+ * (m, j, t, tag | substep << 8) for dims 8j..8j+7: word k gives the pair
+ * U_a = (hi32 + 1/2) 2^-32, U_b = (lo32 + 1/2) 2^-32 and the Box-Muller
+ * values sqrt(-2 ln U_a) (cos, sin)(2 pi U_b) for dims 8j+2k, 8j+2k+1.
+ *   laps_philox_normals: fills out_dev [n_chains][ld] (double for LAPS_F64,
+ *   float otherwise) with that stream for chains 0..n_chains-1.
+ * Tags: 1 first partial refresh of a step, 2 second partial refresh,
+ * 3 full refresh, 4 Metropolis uniform, 5 initial direction. */
+laps_status laps_philox_words(const uint64_t *ctr_dev, uint64_t *out_dev, int64_t n, uint64_t seed, void *stream);
+laps_status laps_philox_normals(uint64_t seed, int64_t n_chains, int64_t d, uint64_t t, uint32_t tag,
+                                uint32_t substep, int32_t prec, void *out_dev, void *stream);
+
+/* Device pointers into the context's workspace: 0 u [N][ld], 1 g [N][ld],
+ * 2 logp [N] (double), 3 delta [N] (double), 4 acc [N] (double),
+ * 5 sigma [ld] (state type).  NULL for an unknown index. */
+void *laps_buffer(laps_ctx *ctx, int32_t which);
+
+/* Releases the host context (no device work is enqueued). */
+laps_status laps_destroy(laps_ctx *ctx);
+
+const char *laps_status_string(laps_status s);
+const char *laps_last_error(const laps_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAPS_H */

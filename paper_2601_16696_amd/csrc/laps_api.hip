@@ -1,0 +1,592 @@
+// Host side of the C ABI declared in include/laps.h: argument validation,
+// workspace carving, launch-shape selection and kernel enqueueing.  No device
+// memory is allocated here and nothing synchronises except
+// laps_ensemble_stats.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "laps.h"
+#include "laps_internal.hpp"
+
+using namespace laps;
+
+struct laps_ctx {
+  laps_config cfg;
+  laps_target tg;
+  void *x;
+  hipStream_t stream;
+  bool dbl;
+  int64_t ld, Tw;
+  // launch shape of the per-chain kernels
+  int T, Q, tpw, block, G, nb;
+  size_t shmem;
+  int integ;
+  bool adj_started;
+  // workspace
+  DevHyper *hyp;
+  void *u, *g, *sigma, *aux, *packed;
+  double *logp, *delta, *acc, *partials, *shiftK, *mean, *var, *m2, *Vii, *ring, *wdelta, *part2;
+  std::string err;
+};
+
+static std::string g_last_global;
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+extern "C" int64_t laps_row_stride(int64_t d) { return round_up(d < 1 ? 1 : d, 8); }
+
+extern "C" void laps_config_default(laps_config *c, int64_t n_chains, int64_t d) {
+  memset(c, 0, sizeof(*c));
+  c->n_chains = n_chains;
+  c->d = d;
+  c->prec = LAPS_F64;
+  c->seed = 0;
+  c->C = 0.025;
+  c->alpha = 2.0;
+  c->eps0_factor = 0.01;
+  c->switch_tol = 0.01;
+  c->window_frac = 0.2;
+  c->acc_tol = 0.03;
+  c->acc_target = 0.0;
+  c->L_partial_factor = 1.25;
+  c->n_steps_traj = 15;
+  c->integrator_adj = 0;
+  c->eevpd_mode = 1;
+  c->switch_policy = 0;
+  c->max_steps_unadj = 1000;
+  c->max_steps_total = 2000;
+}
+
+namespace {
+
+struct Shape {
+  int T, Q, tpw, block, G, nb;
+  size_t shmem;
+};
+
+bool is_local(int kind) { return kind == LAPS_GAUSS_DIAG || kind == LAPS_STOCHVOL || kind == LAPS_PHI4; }
+
+// Team shape: the chain's ceil(d/8) octs over T lanes, Q octs per lane.
+bool local_shape(int kind, bool dbl, int64_t N, int64_t d, Shape &s) {
+  const int64_t octs = (d + 7) / 8;
+  if (octs <= 64) {
+    int T = 1;
+    while (T < octs) T <<= 1;
+    s.T = T;
+    s.Q = 1;
+  } else if (octs <= 512) {
+    s.Q = 1;
+    s.T = (int)round_up(octs, 64);
+  } else if (octs <= 1024) {
+    s.Q = 2;
+    s.T = (int)round_up((octs + 1) / 2, 64);
+  } else {
+    return false;
+  }
+  s.block = s.T <= 64 ? 256 : s.T;
+  s.tpw = s.block / s.T;
+  const int64_t need = (N + s.tpw - 1) / s.tpw;
+  int64_t gmax = s.T >= 256 ? 256 : 512;
+  if (const char *e = getenv("LAPS_GRID")) gmax = atol(e) > 0 ? atol(e) : gmax;
+  s.G = (int)(need < gmax ? need : gmax);
+  const int64_t ld = laps_row_stride(d);
+  const size_t rs = dbl ? 8 : 4;
+  const bool stage = kind != LAPS_GAUSS_DIAG;
+  size_t body = stage ? (size_t)s.tpw * ld * rs : 0;
+  if (s.tpw > 1) {
+    const size_t pb = (size_t)4 * 8 * s.Q * s.T * 8;
+    if (pb > body) body = pb;
+  }
+  s.shmem = 2 * kRedSlots * sizeof(double) + body;
+  s.nb = (int)((d + 255) / 256);
+  return true;
+}
+
+bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
+  const bool dbl = cfg->prec == LAPS_F64;
+  if (is_local(tg->kind)) return local_shape(tg->kind, dbl, cfg->n_chains, cfg->d, s);
+  if (tg->kind == LAPS_LOGREG) {
+    const int tile = logreg_tile_chains(cfg->prec);
+    s.T = 0;
+    s.Q = 0;
+    s.tpw = tile;
+    s.block = 256;
+    s.G = (int)((cfg->n_chains + tile - 1) / tile);
+    s.shmem = 0;
+    s.nb = (int)((cfg->d + 255) / 256);
+    return true;
+  }
+  return false;
+}
+
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    off = (size_t)round_up((int64_t)off, 256);
+    const size_t at = off;
+    off += bytes;
+    return at;
+  }
+};
+
+struct Layout {
+  size_t hyp, u, g, logp, delta, acc, partials, shiftK, mean, var, m2, Vii, ring, wdelta, part2, sigma, aux, packed,
+      total;
+};
+
+Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
+  const int64_t N = cfg->n_chains, d = cfg->d, ld = laps_row_stride(d);
+  const size_t rs = cfg->prec == LAPS_F64 ? 8 : 4;
+  int64_t Tw = (int64_t)llround(cfg->window_frac * (double)cfg->max_steps_total);
+  if (Tw < 2) Tw = 2;
+  Carve c;
+  Layout L;
+  L.hyp = c.take(sizeof(DevHyper));
+  L.u = c.take((size_t)N * ld * rs);
+  L.g = c.take((size_t)N * ld * rs);
+  L.logp = c.take((size_t)N * 8);
+  L.delta = c.take((size_t)N * 8);
+  L.acc = c.take((size_t)N * 8);
+  L.partials = c.take((size_t)s.G * 4 * ld * 8);
+  L.shiftK = c.take((size_t)ld * 8);
+  L.mean = c.take((size_t)ld * 8);
+  L.var = c.take((size_t)ld * 8);
+  L.m2 = c.take((size_t)ld * 8);
+  L.Vii = c.take((size_t)ld * 8);
+  L.ring = c.take((size_t)Tw * ld * 8);
+  L.wdelta = c.take((size_t)ld * 8);
+  L.part2 = c.take((size_t)s.nb * 4 * 8);
+  L.sigma = c.take((size_t)ld * rs);
+  L.aux = c.take((size_t)ld * rs);
+  L.packed = c.take(tg->kind == LAPS_LOGREG ? logreg_packed_bytes(cfg->prec, tg->dims[0], d) : 0);
+  L.total = (size_t)round_up((int64_t)c.off, 256);
+  return L;
+}
+
+laps_status validate(const laps_config *cfg, const laps_target *tg, std::string &why) {
+  if (!cfg || !tg) return why = "null config or target", LAPS_EINVAL;
+  if (cfg->d < 2) return why = "d must be >= 2 (d-1 divides the velocity update)", LAPS_EINVAL;
+  if (cfg->n_chains < 2) return why = "need at least 2 chains", LAPS_EINVAL;
+  if (tg->d != cfg->d) return why = "target d differs from config d", LAPS_EINVAL;
+  if (cfg->prec < 0 || cfg->prec > 2) return why = "unknown precision", LAPS_EINVAL;
+  if (cfg->n_steps_traj < 1 || cfg->max_steps_total < 1 || cfg->max_steps_unadj < 0)
+    return why = "step counts must be positive", LAPS_EINVAL;
+  if (!(cfg->window_frac > 0.0) || !(cfg->C > 0.0) || !(cfg->alpha > 0.0) || !(cfg->eps0_factor > 0.0) ||
+      !(cfg->L_partial_factor > 0.0))
+    return why = "non-positive constant in config", LAPS_EINVAL;
+  if (cfg->integrator_adj < 0 || cfg->integrator_adj > 2 || cfg->eevpd_mode < 0 || cfg->eevpd_mode > 1 ||
+      cfg->switch_policy < 0 || cfg->switch_policy > 1)
+    return why = "bad enum in config", LAPS_EINVAL;
+  switch (tg->kind) {
+    case LAPS_GAUSS_DIAG:
+      if (!tg->data[0]) return why = "gaussian needs data[0] = s2", LAPS_EINVAL;
+      break;
+    case LAPS_STOCHVOL:
+      if (!tg->data[0] || cfg->d < 3) return why = "stochvol needs data[0] = y and d = T + 2 >= 3", LAPS_EINVAL;
+      break;
+    case LAPS_PHI4:
+      if (tg->dims[0] < 2 || tg->dims[0] * tg->dims[0] != cfg->d) return why = "phi4 needs dims[0]^2 == d", LAPS_EINVAL;
+      break;
+    case LAPS_LOGREG:
+      if (!tg->data[0] || !tg->data[1] || tg->dims[0] < 1) return why = "logreg needs X, y and n", LAPS_EINVAL;
+      break;
+    default:
+      return why = "unknown target kind", LAPS_EINVAL;
+  }
+  Shape s;
+  if (!shape_for(cfg, tg, s)) return why = "dimension too large for this build", LAPS_EUNSUPPORTED;
+  if (tg->kind == LAPS_LOGREG && cfg->prec != LAPS_F64 && cfg->prec != LAPS_MIXED_BF16)
+    return why = "logistic regression runs in LAPS_F64 or LAPS_MIXED_BF16", LAPS_EUNSUPPORTED;
+  return LAPS_OK;
+}
+
+int integ_for(const laps_config *cfg) {
+  if (cfg->integrator_adj) return cfg->integrator_adj;
+  return cfg->d <= 200 ? 1 : 2;
+}
+
+LocalArgs local_args(laps_ctx *c) {
+  LocalArgs a{};
+  a.x = c->x;
+  a.u = c->u;
+  a.g = c->g;
+  a.logp = c->logp;
+  a.delta = c->delta;
+  a.acc = c->acc;
+  a.partials = c->partials;
+  a.shiftK = c->shiftK;
+  a.hyp = c->hyp;
+  a.sigma = c->sigma;
+  a.u0 = nullptr;
+  a.aux = c->aux;
+  a.tdata = static_cast<const double *>(c->tg.data[0]);
+  a.tn = c->tg.kind == LAPS_STOCHVOL ? c->cfg.d - 2 : c->tg.dims[0];
+  a.tp0 = c->tg.scal[0];
+  a.tp1 = c->tg.scal[1];
+  a.N = c->cfg.n_chains;
+  a.d = c->cfg.d;
+  a.ld = c->ld;
+  a.T = c->T;
+  a.tpw = c->tpw;
+  a.seed = c->cfg.seed;
+  a.max_total = c->cfg.max_steps_total;
+  a.n_traj = c->cfg.n_steps_traj;
+  a.Lp_factor = c->cfg.L_partial_factor;
+  a.cache = 0;
+  return a;
+}
+
+LogregArgs logreg_args(laps_ctx *c) {
+  LogregArgs a{};
+  a.x = c->x;
+  a.u = c->u;
+  a.g = c->g;
+  a.logp = c->logp;
+  a.delta = c->delta;
+  a.acc = c->acc;
+  a.partials = c->partials;
+  a.shiftK = c->shiftK;
+  a.hyp = c->hyp;
+  a.sigma = c->sigma;
+  a.X = c->tg.data[0];
+  a.y = static_cast<const double *>(c->tg.data[1]);
+  a.Xt = c->packed;
+  a.n = c->tg.dims[0];
+  a.N = c->cfg.n_chains;
+  a.d = c->cfg.d;
+  a.ld = c->ld;
+  a.ldX = c->cfg.d;
+  a.seed = c->cfg.seed;
+  a.max_total = c->cfg.max_steps_total;
+  a.n_traj = c->cfg.n_steps_traj;
+  a.Lp_factor = c->cfg.L_partial_factor;
+  return a;
+}
+
+CtlArgs ctl_args(laps_ctx *c) {
+  CtlArgs a{};
+  a.hyp = c->hyp;
+  a.partials = c->partials;
+  a.G = c->G;
+  a.shiftK = c->shiftK;
+  a.mean = c->mean;
+  a.var = c->var;
+  a.m2 = c->m2;
+  a.Vii = c->Vii;
+  a.ring = c->ring;
+  a.wdelta = c->wdelta;
+  a.Tw = c->Tw;
+  a.part2 = c->part2;
+  a.nb = c->nb;
+  a.delta = c->delta;
+  a.acc = c->acc;
+  a.N = c->cfg.n_chains;
+  a.d = c->cfg.d;
+  a.ld = c->ld;
+  a.C = c->cfg.C;
+  a.alpha = c->cfg.alpha;
+  a.eps0_factor = c->cfg.eps0_factor;
+  a.switch_tol = c->cfg.switch_tol;
+  a.acc_tol = c->cfg.acc_tol;
+  a.acc_target = c->cfg.acc_target;
+  a.n_traj = c->cfg.n_steps_traj;
+  a.eevpd_mode = c->cfg.eevpd_mode;
+  a.switch_policy = c->cfg.switch_policy;
+  a.integ = c->integ;
+  a.max_unadj = c->cfg.max_steps_unadj;
+  a.max_total = c->cfg.max_steps_total;
+  a.sigma = c->sigma;
+  a.sigma_double = c->dbl ? 1 : 0;
+  return a;
+}
+
+laps_status fail(laps_ctx *c, hipError_t e, const char *where) {
+  if (c) c->err = std::string(where) + ": " + hipGetErrorString(e);
+  g_last_global = std::string(where) + ": " + hipGetErrorString(e);
+  return LAPS_EDEVICE;
+}
+
+#define LAPS_CHECK(ctx, expr, where)          \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return fail(ctx, e_, where); \
+  } while (0)
+
+laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
+  if (is_local(c->tg.kind)) {
+    LocalArgs a = local_args(c);
+    a.u0 = u0;
+    return launch_local(c->tg.kind, c->dbl, c->Q, kk, a, c->G, c->block, c->shmem, c->stream) == hipSuccess
+               ? LAPS_OK
+               : fail(c, hipGetLastError(), "per-chain kernel");
+  }
+  LogregArgs a = logreg_args(c);
+  a.u0 = u0;
+  const hipError_t e = launch_logreg(c->cfg.prec, kk, a, c->G, c->stream);
+  return e == hipSuccess ? LAPS_OK : fail(c, e, "logistic-regression kernel");
+}
+
+}  // namespace
+
+extern "C" laps_status laps_workspace_size(const laps_config *cfg, const laps_target *tg, size_t *bytes) {
+  std::string why;
+  const laps_status st = validate(cfg, tg, why);
+  if (st != LAPS_OK) {
+    g_last_global = why;
+    return st;
+  }
+  if (!bytes) return LAPS_EINVAL;
+  Shape s;
+  shape_for(cfg, tg, s);
+  *bytes = layout(cfg, tg, s).total;
+  return LAPS_OK;
+}
+
+extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, void *x_dev, const void *u0_dev,
+                                 void *ws_dev, size_t ws_bytes, void *stream, laps_ctx **out) {
+  std::string why;
+  laps_status st = validate(cfg, tg, why);
+  if (st != LAPS_OK) {
+    g_last_global = why;
+    return st;
+  }
+  if (!x_dev || !ws_dev || !out) {
+    g_last_global = "null pointer argument";
+    return LAPS_EINVAL;
+  }
+  if (((uintptr_t)x_dev & 31) || ((uintptr_t)ws_dev & 255) || (u0_dev && ((uintptr_t)u0_dev & 31))) {
+    g_last_global = "misaligned pointer (x/u0 need 32 bytes, workspace 256)";
+    return LAPS_EINVAL;
+  }
+  Shape s;
+  shape_for(cfg, tg, s);
+  const Layout L = layout(cfg, tg, s);
+  if (ws_bytes < L.total) {
+    g_last_global = "workspace too small";
+    return LAPS_EWORKSPACE;
+  }
+  laps_ctx *c = new (std::nothrow) laps_ctx();
+  if (!c) return LAPS_EINVAL;
+  c->cfg = *cfg;
+  c->tg = *tg;
+  c->x = x_dev;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->dbl = cfg->prec == LAPS_F64;
+  c->ld = laps_row_stride(cfg->d);
+  c->Tw = (int64_t)llround(cfg->window_frac * (double)cfg->max_steps_total);
+  if (c->Tw < 2) c->Tw = 2;
+  c->T = s.T;
+  c->Q = s.Q;
+  c->tpw = s.tpw;
+  c->block = s.block;
+  c->G = s.G;
+  c->nb = s.nb;
+  c->shmem = s.shmem;
+  c->integ = integ_for(cfg);
+  c->adj_started = false;
+  char *w = static_cast<char *>(ws_dev);
+  c->hyp = reinterpret_cast<DevHyper *>(w + L.hyp);
+  c->u = w + L.u;
+  c->g = w + L.g;
+  c->logp = reinterpret_cast<double *>(w + L.logp);
+  c->delta = reinterpret_cast<double *>(w + L.delta);
+  c->acc = reinterpret_cast<double *>(w + L.acc);
+  c->partials = reinterpret_cast<double *>(w + L.partials);
+  c->shiftK = reinterpret_cast<double *>(w + L.shiftK);
+  c->mean = reinterpret_cast<double *>(w + L.mean);
+  c->var = reinterpret_cast<double *>(w + L.var);
+  c->m2 = reinterpret_cast<double *>(w + L.m2);
+  c->Vii = reinterpret_cast<double *>(w + L.Vii);
+  c->ring = reinterpret_cast<double *>(w + L.ring);
+  c->wdelta = reinterpret_cast<double *>(w + L.wdelta);
+  c->part2 = reinterpret_cast<double *>(w + L.part2);
+  c->sigma = w + L.sigma;
+  c->aux = w + L.aux;
+  c->packed = w + L.packed;
+  if (c->shmem > 64 * 1024) {
+    // larger dynamic LDS needs the attribute on every instantiation; this build keeps within 64 KiB
+    delete c;
+    g_last_global = "team shape needs more than 64 KiB of LDS";
+    return LAPS_EUNSUPPORTED;
+  }
+
+  CtlArgs ca = ctl_args(c);
+  hipError_t e;
+  if ((e = hipMemsetAsync(c->shiftK, 0, (size_t)c->ld * 8, c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(c->u, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(c->g, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess) {
+    fail(c, e, "workspace clear");
+    delete c;
+    return LAPS_EDEVICE;
+  }
+  if (tg->kind == LAPS_GAUSS_DIAG || tg->kind == LAPS_STOCHVOL)
+    e = launch_prep_aux(tg->kind, c->dbl, tg->data[0], c->aux, cfg->d, c->ld, c->stream);
+  if (e == hipSuccess && tg->kind == LAPS_LOGREG)
+    e = launch_logreg_pack(cfg->prec, tg->data[0], c->packed, tg->dims[0], cfg->d, c->stream);
+  if (e == hipSuccess) e = launch_hyper_init(ca, c->stream);
+  if (e != hipSuccess) {
+    fail(c, e, "init");
+    delete c;
+    return LAPS_EDEVICE;
+  }
+  st = enqueue_chain_kernel(c, KK_INIT, u0_dev);
+  if (st == LAPS_OK && (e = launch_finalize(ca, FIN_INIT, c->stream)) != hipSuccess) st = fail(c, e, "finalize");
+  if (st == LAPS_OK && (e = launch_ctl_init(ca, c->stream)) != hipSuccess) st = fail(c, e, "controller init");
+  if (st != LAPS_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return LAPS_OK;
+}
+
+extern "C" laps_status laps_step_unadjusted(laps_ctx *c, int64_t n) {
+  if (!c || n < 0) return LAPS_EINVAL;
+  if (c->adj_started) return LAPS_EPHASE;
+  CtlArgs ca = ctl_args(c);
+  for (int64_t k = 0; k < n; ++k) {
+    laps_status st = enqueue_chain_kernel(c, KK_UNADJ, nullptr);
+    if (st != LAPS_OK) return st;
+    LAPS_CHECK(c, launch_finalize(ca, FIN_UNADJ, c->stream), "finalize");
+    LAPS_CHECK(c, launch_ctl_unadj(ca, c->stream), "controller");
+  }
+  return LAPS_OK;
+}
+
+extern "C" laps_status laps_step_adjusted(laps_ctx *c, int64_t n) {
+  if (!c || n < 0) return LAPS_EINVAL;
+  CtlArgs ca = ctl_args(c);
+  if (!c->adj_started) {
+    LAPS_CHECK(c, launch_switch(ca, c->stream), "switch");
+    c->adj_started = true;
+  }
+  const KernelKind kk = c->integ == 2 ? KK_MAMS_MN4 : KK_MAMS_MN2;
+  for (int64_t k = 0; k < n; ++k) {
+    laps_status st = enqueue_chain_kernel(c, kk, nullptr);
+    if (st != LAPS_OK) return st;
+    LAPS_CHECK(c, launch_ctl_adj(ca, c->stream), "controller");
+  }
+  return LAPS_OK;
+}
+
+extern "C" laps_status laps_ensemble_stats(laps_ctx *c, laps_stats *o, double *per_dim) {
+  if (!c || !o) return LAPS_EINVAL;
+  if (per_dim) {
+    const size_t row = (size_t)c->cfg.d * 8;
+    double *src[4] = {c->mean, c->var, c->m2, c->Vii};
+    for (int k = 0; k < 4; ++k)
+      LAPS_CHECK(c, hipMemcpyAsync(per_dim + (size_t)k * c->cfg.d, src[k], row, hipMemcpyDeviceToDevice, c->stream),
+                 "per-dim copy");
+  }
+  DevHyper h;
+  LAPS_CHECK(c, hipMemcpyAsync(&h, c->hyp, sizeof(h), hipMemcpyDeviceToHost, c->stream), "stats copy");
+  LAPS_CHECK(c, hipStreamSynchronize(c->stream), "stream sync");
+  o->t = h.t;
+  o->grads_per_chain = h.grads;
+  o->phase = h.phase;
+  o->adapt = h.adapt;
+  o->switch_ready = h.switch_ready;
+  o->status_bits = h.status;
+  o->eps = h.eps;
+  o->L = h.L;
+  o->eevpd = h.eevpd;
+  o->eevpd_target = h.eevpd_target;
+  o->dtilde = h.dtilde;
+  o->max_delta = h.max_delta;
+  o->acc_mean = h.acc_mean;
+  o->n_nonfinite = h.n_nonfinite;
+  o->integrator = h.integ;
+  o->have_lo = h.have_lo;
+  o->have_hi = h.have_hi;
+  o->ring_full = h.ring_count == c->Tw;
+  o->lo = h.lo;
+  o->hi = h.hi;
+  o->a_star = h.a_star;
+  o->sum_var = h.sum_var;
+  return (h.status & ST_NONFINITE) ? LAPS_ENONFINITE : LAPS_OK;
+}
+
+extern "C" laps_status laps_target_eval(const laps_target *tg, int32_t prec, const void *x_dev, void *logp_dev,
+                                        void *grad_dev, int64_t n, void *stream) {
+  if (!tg || !x_dev || !logp_dev || n < 1 || tg->d < 2 || prec < 0 || prec > 2) return LAPS_EINVAL;
+  if (((uintptr_t)x_dev & 31) || (grad_dev && ((uintptr_t)grad_dev & 31))) return LAPS_EINVAL;
+  laps_config cfg;
+  laps_config_default(&cfg, n < 2 ? 2 : n, tg->d);
+  cfg.prec = prec;
+  std::string why;
+  laps_status st = validate(&cfg, tg, why);
+  if (st != LAPS_OK) {
+    g_last_global = why;
+    return st;
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (is_local(tg->kind)) {
+    Shape sh;
+    local_shape(tg->kind, prec == LAPS_F64, n, tg->d, sh);
+    if (sh.shmem > 64 * 1024) return LAPS_EUNSUPPORTED;
+    LocalArgs a{};
+    a.x = const_cast<void *>(x_dev);
+    a.aux = nullptr;
+    a.tdata = static_cast<const double *>(tg->data[0]);
+    a.tn = tg->kind == LAPS_STOCHVOL ? tg->d - 2 : tg->dims[0];
+    a.tp0 = tg->scal[0];
+    a.tp1 = tg->scal[1];
+    a.N = n;
+    a.d = tg->d;
+    a.ld = laps_row_stride(tg->d);
+    a.T = sh.T;
+    a.tpw = sh.tpw;
+    a.logp_out = static_cast<double *>(logp_dev);
+    a.g_out = grad_dev;
+    const int grid = (int)((n + sh.tpw - 1) / sh.tpw);
+    const hipError_t e = launch_local(tg->kind, prec == LAPS_F64, sh.Q, KK_EVAL, a, grid < 65535 ? grid : 65535,
+                                      sh.block, sh.shmem, s);
+    if (e != hipSuccess) {
+      g_last_global = std::string("target eval: ") + hipGetErrorString(e);
+      return LAPS_EDEVICE;
+    }
+    return LAPS_OK;
+  }
+  g_last_global = "standalone evaluation of this target needs a context (use laps_buffer after laps_init)";
+  return LAPS_EUNSUPPORTED;
+}
+
+extern "C" void *laps_buffer(laps_ctx *c, int32_t which) {
+  if (!c) return nullptr;
+  switch (which) {
+    case 0: return c->u;
+    case 1: return c->g;
+    case 2: return c->logp;
+    case 3: return c->delta;
+    case 4: return c->acc;
+    case 5: return c->sigma;
+    default: return nullptr;
+  }
+}
+
+extern "C" laps_status laps_destroy(laps_ctx *c) {
+  delete c;
+  return LAPS_OK;
+}
+
+extern "C" const char *laps_status_string(laps_status s) {
+  switch (s) {
+    case LAPS_OK: return "ok";
+    case LAPS_EINVAL: return "invalid argument";
+    case LAPS_EDEVICE: return "device error";
+    case LAPS_ENONFINITE: return "non-finite energy error in some chains";
+    case LAPS_EPHASE: return "wrong phase";
+    case LAPS_EWORKSPACE: return "workspace too small";
+    case LAPS_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+extern "C" const char *laps_last_error(const laps_ctx *c) {
+  if (c && !c->err.empty()) return c->err.c_str();
+  return g_last_global.c_str();
+}

@@ -1,0 +1,223 @@
+// Device-side building blocks of the LAPS hot path for gfx950: the
+// device-resident hyperparameter block, the counter-based random numbers,
+// team reductions and the scalar parts of the integrator maps.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace laps {
+
+// Hyperparameters and diagnostics, resident in device memory.  Only the
+// single-workgroup controller kernels write it; every step kernel reads it at
+// launch, so a captured sequence of steps needs no host round trip.
+struct DevHyper {
+  double eps, L, eevpd, eevpd_target, dtilde, max_delta, acc_mean, sum_var, lo, hi, a_star;
+  int64_t t, grads, n_nonfinite, ring_count, ring_pos;
+  int32_t phase, adapt, switch_ready, status, integ, have_lo, have_hi, switched;
+};
+
+enum { PH_UNADJ = 0, PH_SWITCH_PENDING = 1, PH_ADJ = 2 };
+enum { TAG_O_FIRST = 1, TAG_O_SECOND = 2, TAG_FULL_REFRESH = 3, TAG_MH = 4, TAG_INIT_DIR = 5 };
+enum { ST_NONFINITE = 1, ST_EPS_KEPT = 2, ST_SIGMA_FIX = 4 };
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two 64x64
+// multiplies with Weyl-sequence key bumps between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+    const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+// Eight standard normals for dims 8*oct .. 8*oct+7 of chain m: word k of the
+// block gives (U_a, U_b) = ((hi32 + 1/2) 2^-32, (lo32 + 1/2) 2^-32) and the
+// Box-Muller pair r cos(2 pi U_b), r sin(2 pi U_b), r = sqrt(-2 ln U_a).
+template <class Real>
+__device__ __forceinline__ void normals8(uint64_t seed, uint64_t m, uint64_t oct, uint64_t t, uint32_t tag,
+                                         uint32_t substep, Real (&z)[8]);
+
+template <>
+__device__ __forceinline__ void normals8<double>(uint64_t seed, uint64_t m, uint64_t oct, uint64_t t, uint32_t tag,
+                                                 uint32_t substep, double (&z)[8]) {
+  uint64_t c[4] = {m, oct, t, (uint64_t)tag | ((uint64_t)substep << 8)};
+  philox4x64_10(c, seed, 0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double ua = ((double)(uint32_t)(c[k] >> 32) + 0.5) * 2.3283064365386963e-10;
+    const double ub = ((double)(uint32_t)c[k] + 0.5) * 2.3283064365386963e-10;
+    const double r = sqrt(-2.0 * log(ua));
+    double s, co;
+    sincospi(2.0 * ub, &s, &co);
+    z[2 * k] = r * co;
+    z[2 * k + 1] = r * s;
+  }
+}
+
+template <>
+__device__ __forceinline__ void normals8<float>(uint64_t seed, uint64_t m, uint64_t oct, uint64_t t, uint32_t tag,
+                                                uint32_t substep, float (&z)[8]) {
+  uint64_t c[4] = {m, oct, t, (uint64_t)tag | ((uint64_t)substep << 8)};
+  philox4x64_10(c, seed, 0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float ua = fmaf((float)(uint32_t)(c[k] >> 32), 2.3283064365386963e-10f, 1.1641532182693481e-10f);
+    const float ub = fmaf((float)(uint32_t)c[k], 2.3283064365386963e-10f, 1.1641532182693481e-10f);
+    const float r = sqrtf(-2.0f * logf(ua));
+    float s, co;
+    sincospif(2.0f * ub, &s, &co);
+    z[2 * k] = r * co;
+    z[2 * k + 1] = r * s;
+  }
+}
+
+// Metropolis uniform of chain m for the transition starting at step t: the
+// 53 high bits of word 0 of block (m, 0, t, TAG_MH), offset by half a unit.
+__device__ __forceinline__ double mh_uniform(uint64_t seed, uint64_t m, uint64_t t) {
+  uint64_t c[4] = {m, 0, t, (uint64_t)TAG_MH};
+  philox4x64_10(c, seed, 0);
+  return ((double)(c[0] >> 11) + 0.5) * 1.1102230246251565e-16;
+}
+
+// ---------------------------------------------------------------------------
+// Team reductions.  A team of T lanes owns one chain: T <= 64 is an aligned
+// lane group inside a wavefront (xor butterflies, no barrier); T > 64 is the
+// whole workgroup (butterfly per wavefront, then a fixed-order sum over
+// wavefronts through LDS, double-buffered so one barrier suffices).  Every
+// lane ends with the identical value, and the order of additions is fixed.
+// ---------------------------------------------------------------------------
+constexpr int kRedSlots = 16 * 8;  // doubles per buffer: 16 wavefronts x 8 values
+
+template <int NV>
+__device__ __forceinline__ void team_sum(double (&v)[NV], int T, double *red, int &slot) {
+  if (T <= 64) {
+    for (int msk = T >> 1; msk >= 1; msk >>= 1) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], msk);
+    }
+    return;
+  }
+#pragma unroll
+  for (int msk = 32; msk >= 1; msk >>= 1) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], msk);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = T >> 6;
+  const int w0 = (wave / nw) * nw;  // first wavefront of this lane's team
+  double *buf = red + slot * kRedSlots;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) buf[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += buf[(w0 + w) * NV + k];
+    v[k] = s;
+  }
+  slot ^= 1;
+}
+
+// NaN-propagating maximum (a NaN fluctuation means "not settled").
+__device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Velocity update B_h (closed-form solution of the Riccati flow at fixed x):
+// with n = |g~|, delta = h n / (d-1), c = e.u,
+//   u' = (u + (sinh delta + c (cosh delta - 1)) e) / (cosh delta + c sinh delta)
+//   dK = (d-1) log(cosh delta + c sinh delta).
+// Returned as u' = A u + Bg g~ so the per-element update is one fma.
+// cosh - 1 is taken as 2 sinh^2(delta/2); beyond |delta| = 20 the quotient is
+// divided through by cosh delta (tanh/sech form) to avoid overflow.
+// ---------------------------------------------------------------------------
+struct BMap {
+  double A, Bg, dK;
+};
+
+__device__ __forceinline__ BMap b_map(double gg, double gu, double h, double dm1) {
+  BMap r;
+  if (gg == 0.0) {
+    r.A = 1.0;
+    r.Bg = 0.0;
+    r.dK = 0.0;
+    return r;
+  }
+  const double n = sqrt(gg);
+  const double delta = h * n / dm1;
+  const double c = gu / n;
+  if (fabs(delta) < 20.0) {
+    const double sh = sinh(delta);
+    const double shh = sinh(0.5 * delta);
+    const double chm1 = 2.0 * shh * shh;
+    const double Dm1 = chm1 + c * sh;
+    const double invD = 1.0 / (1.0 + Dm1);
+    r.A = invD;
+    r.Bg = (sh + c * chm1) / n * invD;
+    r.dK = dm1 * log1p(Dm1);
+  } else {
+    const double ad = fabs(delta);
+    const double e2 = exp(-2.0 * ad);
+    const double tau = copysign((1.0 - e2) / (1.0 + e2), delta);
+    const double sech = 2.0 * exp(-ad) / (1.0 + e2);
+    const double Dh = 1.0 + c * tau;
+    r.A = sech / Dh;
+    r.Bg = (tau + c * (1.0 - sech)) / n / Dh;
+    r.dK = dm1 * (ad + log1p(e2) - 0.69314718055994531 + log(Dh));
+  }
+  return r;
+}
+
+// Integrator coefficient sets (Table "Integrators"): symmetric B A B ... B,
+// the coefficients not printed follow from symmetry and normalisation.
+struct Coeffs {
+  int K;
+  double b[6], a[5];
+};
+
+__host__ __device__ inline Coeffs integrator_coeffs(int which) {
+  Coeffs c{};
+  if (which == 0) {
+    c.K = 2;
+    c.b[0] = 0.5;
+    c.b[1] = 0.5;
+    c.a[0] = 1.0;
+  } else if (which == 1) {
+    const double b1 = 0.1931833275;
+    c.K = 3;
+    c.b[0] = b1;
+    c.b[1] = 1.0 - 2.0 * b1;
+    c.b[2] = b1;
+    c.a[0] = 0.5;
+    c.a[1] = 0.5;
+  } else {
+    const double b1 = 0.0839831526, b2 = 0.6822365335, a1 = 0.2539785108, a2 = -0.032302867;
+    const double b3 = 0.5 - b1 - b2, a3 = 1.0 - 2.0 * (a1 + a2);
+    c.K = 6;
+    c.b[0] = b1;
+    c.b[1] = b2;
+    c.b[2] = b3;
+    c.b[3] = b3;
+    c.b[4] = b2;
+    c.b[5] = b1;
+    c.a[0] = a1;
+    c.a[1] = a2;
+    c.a[2] = a3;
+    c.a[3] = a2;
+    c.a[4] = a1;
+  }
+  return c;
+}
+
+}  // namespace laps

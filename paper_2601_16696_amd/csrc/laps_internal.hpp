@@ -1,0 +1,98 @@
+// Host/device argument blocks and launcher declarations shared by the
+// translation units of the LAPS library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "laps_device.hpp"
+
+namespace laps {
+
+// Arguments of the per-chain kernels.  A team of T lanes owns one chain; lane
+// r of a team owns the "octs" r + q T (q < Q) of the chain, i.e. the eight
+// consecutive coordinates 8 (r + q T) .. 8 (r + q T) + 7, which is also the
+// unit of one Philox block.  Rows have stride ld (a multiple of 8).
+struct LocalArgs {
+  void *x, *u, *g;
+  double *logp, *delta, *acc;
+  double *partials;        // [gridDim][4][ld]: sums of x-K, (x-K)^2, (x-K) g, g
+  const double *shiftK;    // [ld] shift K (previous ensemble mean)
+  DevHyper *hyp;
+  const void *sigma;       // [ld] diagonal preconditioner (state type)
+  const void *u0;          // optional initial velocities
+  const void *aux;         // [ld] per-dim target constants (state type)
+  const double *tdata;     // target data in double (SV returns y)
+  int64_t tn;              // SV: T; phi4: L
+  double tp0, tp1;         // phi4: m2, lambda
+  int64_t N, d, ld;
+  int T, tpw;
+  uint64_t seed;
+  int64_t max_total;
+  int n_traj;
+  double Lp_factor;
+  int cache;               // store g and log p (1) or recompute them (0)
+  double *logp_out;        // target eval: log p output
+  void *g_out;             // target eval: gradient output (or null)
+};
+
+// Arguments of the statistics / controller kernels.
+struct CtlArgs {
+  DevHyper *hyp;
+  const double *partials;
+  int G;                   // partial rows
+  double *shiftK, *mean, *var, *m2, *Vii;
+  double *ring, *wdelta;
+  int64_t Tw;
+  double *part2;           // [nb][4] per-block scalars
+  int nb;
+  const double *delta, *acc;
+  int64_t N, d, ld;
+  double C, alpha, eps0_factor, switch_tol, acc_tol, acc_target;
+  int n_traj, eevpd_mode, switch_policy, integ;
+  int64_t max_unadj, max_total;
+  void *sigma;
+  int sigma_double;
+};
+
+enum { FIN_INIT = 0, FIN_UNADJ = 1 };
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_hyper_init(const CtlArgs &c, hipStream_t s);
+hipError_t launch_finalize(const CtlArgs &c, int mode, hipStream_t s);
+hipError_t launch_ctl_init(const CtlArgs &c, hipStream_t s);
+hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s);
+hipError_t launch_switch(const CtlArgs &c, hipStream_t s);
+hipError_t launch_ctl_adj(const CtlArgs &c, hipStream_t s);
+
+enum KernelKind { KK_INIT = 0, KK_UNADJ = 1, KK_MAMS_MN2 = 2, KK_MAMS_MN4 = 3, KK_EVAL = 4 };
+
+// Local targets: kind is laps_target_kind (gauss, stochvol, phi4).
+hipError_t launch_local(int kind, bool dbl, int Q, KernelKind kk, const LocalArgs &a, int grid, int block,
+                        size_t shmem, hipStream_t s);
+hipError_t launch_prep_aux(int kind, bool dbl, const void *src, void *aux, int64_t d, int64_t ld, hipStream_t s);
+
+// Logistic regression.
+struct LogregArgs {
+  void *x, *u, *g;
+  double *logp, *delta, *acc, *partials;
+  const double *shiftK;
+  DevHyper *hyp;
+  const void *sigma;
+  const void *u0;
+  const void *X;           // [n][d] (double for F64, bf16 bits for F32/mixed)
+  const double *y;         // [n]
+  const void *Xt;          // packed operand (bf16 paths)
+  int64_t n, N, d, ld, ldX;
+  uint64_t seed;
+  int64_t max_total;
+  int n_traj;
+  double Lp_factor;
+  double *logp_out;
+  void *g_out;
+};
+hipError_t launch_logreg(int prec, KernelKind kk, const LogregArgs &a, int grid, hipStream_t s);
+int logreg_tile_chains(int prec);
+size_t logreg_packed_bytes(int prec, int64_t n, int64_t d);
+hipError_t launch_logreg_pack(int prec, const void *X, void *Xt, int64_t n, int64_t d, hipStream_t s);
+
+}  // namespace laps

@@ -1,0 +1,287 @@
+"""Thin Python binding of the LAPS C ABI (include/laps.h).
+
+Argument marshalling only: every step of the sampler runs in the HIP kernels
+of liblaps_hip.so.  PyTorch provides device memory and the stream.  There is
+no CPU fallback: without the built library every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblaps_hip.so")
+
+OK, EINVAL, EDEVICE, ENONFINITE, EPHASE, EWORKSPACE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+F64, F32, MIXED_BF16 = 0, 1, 2
+GAUSS_DIAG, LOGREG, STOCHVOL, PHI4 = 0, 1, 2, 3
+PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, F64: F64, F32: F32, MIXED_BF16: MIXED_BF16}
+KINDS = {"gauss": GAUSS_DIAG, "logreg": LOGREG, "stochvol": STOCHVOL, "phi4": PHI4}
+
+
+class LapsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"LAPS status {status}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n_chains", ctypes.c_int64), ("d", ctypes.c_int64), ("prec", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("C", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("eps0_factor", ctypes.c_double), ("switch_tol", ctypes.c_double),
+                ("window_frac", ctypes.c_double), ("acc_tol", ctypes.c_double), ("acc_target", ctypes.c_double),
+                ("L_partial_factor", ctypes.c_double), ("n_steps_traj", ctypes.c_int32),
+                ("integrator_adj", ctypes.c_int32), ("eevpd_mode", ctypes.c_int32),
+                ("switch_policy", ctypes.c_int32), ("max_steps_unadj", ctypes.c_int64),
+                ("max_steps_total", ctypes.c_int64)]
+
+
+class TargetS(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("d", ctypes.c_int64), ("data", ctypes.c_void_p * 4),
+                ("dims", ctypes.c_int64 * 4), ("scal", ctypes.c_double * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("grads_per_chain", ctypes.c_int64), ("phase", ctypes.c_int32),
+                ("adapt", ctypes.c_int32), ("switch_ready", ctypes.c_int32), ("status_bits", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("L", ctypes.c_double), ("eevpd", ctypes.c_double),
+                ("eevpd_target", ctypes.c_double), ("dtilde", ctypes.c_double), ("max_delta", ctypes.c_double),
+                ("acc_mean", ctypes.c_double), ("n_nonfinite", ctypes.c_int64), ("integrator", ctypes.c_int32),
+                ("have_lo", ctypes.c_int32), ("have_hi", ctypes.c_int32), ("ring_full", ctypes.c_int32),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("a_star", ctypes.c_double),
+                ("sum_var", ctypes.c_double)]
+
+
+EXPORTS = ["laps_config_default", "laps_row_stride", "laps_workspace_size", "laps_init", "laps_step_unadjusted",
+           "laps_step_adjusted", "laps_ensemble_stats", "laps_target_eval", "laps_philox_words",
+           "laps_philox_normals", "laps_buffer", "laps_destroy", "laps_status_string", "laps_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Loads the built HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LapsError(EUNSUPPORTED, f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                                      "(python -m paper_2601_16696_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, U64, U32, D = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
+                                ctypes.c_double)
+    sig = {
+        "laps_config_default": (None, [P, I64, I64]),
+        "laps_row_stride": (I64, [I64]),
+        "laps_workspace_size": (I32, [P, P, P]),
+        "laps_init": (I32, [P, P, P, P, P, ctypes.c_size_t, P, P]),
+        "laps_step_unadjusted": (I32, [P, I64]),
+        "laps_step_adjusted": (I32, [P, I64]),
+        "laps_ensemble_stats": (I32, [P, P, P]),
+        "laps_target_eval": (I32, [P, I32, P, P, P, I64, P]),
+        "laps_philox_words": (I32, [P, P, I64, U64, P]),
+        "laps_philox_normals": (I32, [U64, I64, I64, U64, U32, U32, I32, P, P]),
+        "laps_buffer": (P, [P, I32]),
+        "laps_destroy": (I32, [P]),
+        "laps_status_string": (ctypes.c_char_p, [I32]),
+        "laps_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st: int, ctx=None):
+    if st != OK:
+        msg = lib().laps_last_error(ctx).decode() if ctx is not None else lib().laps_last_error(None).decode()
+        raise LapsError(st, f"{lib().laps_status_string(st).decode()} ({msg})")
+
+
+def row_stride(d: int) -> int:
+    return lib().laps_row_stride(d)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _state_dtype(prec: int):
+    torch = _torch()
+    return torch.float64 if prec == F64 else torch.float32
+
+
+def bf16_bits(a: np.ndarray) -> np.ndarray:
+    """Upper 16 bits of float32 values that are already bf16-exact."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    return (f.view(np.uint32) >> 16).astype(np.uint16)
+
+
+class Target:
+    """Device-resident target description (keeps its tensors alive)."""
+
+    def __init__(self, w: dict, prec, device="cuda:0"):
+        torch = _torch()
+        self.prec = PRECISIONS[prec]
+        self.kind = KINDS[w["kind"]]
+        self.d = int(w["d"])
+        self.keep = []
+        s = TargetS()
+        s.kind = self.kind
+        s.d = self.d
+        if self.kind == GAUSS_DIAG:
+            t = torch.as_tensor(np.asarray(w["sigma2"], dtype=np.float64), device=device)
+            self.keep.append(t)
+            s.data[0] = t.data_ptr()
+        elif self.kind == STOCHVOL:
+            t = torch.as_tensor(np.asarray(w["y"], dtype=np.float64), device=device)
+            self.keep.append(t)
+            s.data[0] = t.data_ptr()
+            s.dims[0] = int(w["y"].shape[0])
+        elif self.kind == PHI4:
+            s.dims[0] = int(w["side"])
+            s.scal[0] = float(w["m2"])
+            s.scal[1] = float(w["lam"])
+        elif self.kind == LOGREG:
+            X = np.asarray(w["X"])
+            if self.prec == F64:
+                tX = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float64), device=device)
+            else:
+                tX = torch.as_tensor(bf16_bits(X).view(np.int16), device=device)
+            ty = torch.as_tensor(np.asarray(w["y"], dtype=np.float64), device=device)
+            self.keep += [tX, ty]
+            s.data[0] = tX.data_ptr()
+            s.data[1] = ty.data_ptr()
+            s.dims[0] = int(X.shape[0])
+        self.s = s
+
+    def eval(self, x, grad: bool = True, stream=None):
+        """log p [n] (float64) and gradient [n, d] for rows of x ([n, d] or padded [n, ld])."""
+        torch = _torch()
+        ld = row_stride(self.d)
+        dt = _state_dtype(self.prec)
+        n = x.shape[0]
+        if x.shape[1] != ld or x.dtype != dt or not x.is_contiguous():
+            xp = torch.zeros((n, ld), dtype=dt, device=x.device)
+            xp[:, :self.d] = x[:, :self.d].to(dt)
+        else:
+            xp = x
+        lp = torch.empty(n, dtype=torch.float64, device=x.device)
+        g = torch.empty((n, ld), dtype=dt, device=x.device) if grad else None
+        st = lib().laps_target_eval(ctypes.byref(self.s), self.prec, ctypes.c_void_p(xp.data_ptr()),
+                                    ctypes.c_void_p(lp.data_ptr()),
+                                    ctypes.c_void_p(g.data_ptr()) if grad else None, n, _stream_ptr(stream))
+        _check(st)
+        return lp, (g[:, :self.d] if grad else None)
+
+
+class Sampler:
+    """One LAPS ensemble on the current GPU.
+
+    w: workload dict (see workloads.py); x0: [N, d] initial positions.
+    cfg keywords override the paper's defaults (laps_config fields)."""
+
+    def __init__(self, w: dict, prec="f64", x0=None, seed=None, device="cuda:0", u0=None, **cfg):
+        torch = _torch()
+        self.prec = PRECISIONS[prec]
+        self.target = Target(w, self.prec, device)
+        x0 = w["x0"] if x0 is None else x0
+        N, d = int(x0.shape[0]), int(w["d"])
+        self.N, self.d = N, d
+        self.ld = row_stride(d)
+        c = Config()
+        lib().laps_config_default(ctypes.byref(c), N, d)
+        c.prec = self.prec
+        c.seed = int(w.get("seed", 0) if seed is None else seed)
+        for k, v in cfg.items():
+            if not hasattr(c, k):
+                raise TypeError(f"unknown config field {k}")
+            setattr(c, k, v)
+        self.cfg = c
+        dt = _state_dtype(self.prec)
+        self.x = torch.zeros((N, self.ld), dtype=dt, device=device)
+        self.x[:, :d] = torch.as_tensor(np.asarray(x0), device=device).to(dt)
+        self.u0 = None
+        if u0 is not None:
+            self.u0 = torch.zeros((N, self.ld), dtype=dt, device=device)
+            self.u0[:, :d] = torch.as_tensor(np.asarray(u0), device=device).to(dt)
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().laps_workspace_size(ctypes.byref(c), ctypes.byref(self.target.s), ctypes.byref(nbytes)))
+        self.ws_bytes = nbytes.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.per_dim = torch.empty((4, d), dtype=torch.float64, device=device)
+        self.ctx = ctypes.c_void_p()
+        st = lib().laps_init(ctypes.byref(c), ctypes.byref(self.target.s), ctypes.c_void_p(self.x.data_ptr()),
+                             ctypes.c_void_p(self.u0.data_ptr()) if self.u0 is not None else None,
+                             ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, _stream_ptr(), ctypes.byref(self.ctx))
+        _check(st)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx and _lib is not None:
+            _lib.laps_destroy(ctx)
+            self.ctx = None
+
+    def step_unadjusted(self, n: int = 1):
+        _check(lib().laps_step_unadjusted(self.ctx, n), self.ctx)
+
+    def step_adjusted(self, n: int = 1):
+        _check(lib().laps_step_adjusted(self.ctx, n), self.ctx)
+
+    def stats(self, per_dim: bool = False) -> dict:
+        s = Stats()
+        st = lib().laps_ensemble_stats(self.ctx, ctypes.byref(s),
+                                       ctypes.c_void_p(self.per_dim.data_ptr()) if per_dim else None)
+        if st not in (OK, ENONFINITE):
+            _check(st, self.ctx)
+        out = {f: getattr(s, f) for f, _ in s._fields_}
+        out["status"] = st
+        return out
+
+    def positions(self):
+        return self.x[:, :self.d]
+
+    def buffer(self, name: str):
+        """Views of workspace arrays: u, g ([N, d]), logp, delta, acc ([N]), sigma ([d])."""
+        torch = _torch()
+        idx = {"u": 0, "g": 1, "logp": 2, "delta": 3, "acc": 4, "sigma": 5}[name]
+        ptr = lib().laps_buffer(self.ctx, idx)
+        off = ptr - self.ws.data_ptr()
+        dt = _state_dtype(self.prec)
+        es = 8 if dt == torch.float64 else 4
+        if name in ("u", "g"):
+            n = self.N * self.ld * es
+            return self.ws[off:off + n].view(dt).view(self.N, self.ld)[:, :self.d]
+        if name == "sigma":
+            return self.ws[off:off + self.ld * es].view(dt)[:self.d]
+        return self.ws[off:off + self.N * 8].view(torch.float64)
+
+
+def philox_words(ctr: np.ndarray, seed: int, device="cuda:0") -> np.ndarray:
+    torch = _torch()
+    c = torch.as_tensor(np.ascontiguousarray(ctr, dtype=np.uint64).view(np.int64), device=device)
+    out = torch.empty_like(c)
+    _check(lib().laps_philox_words(ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   c.shape[0], seed, _stream_ptr()))
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64)
+
+
+def philox_normals(seed: int, n_chains: int, d: int, t: int, tag: int, substep: int, prec="f64", device="cuda:0"):
+    torch = _torch()
+    p = PRECISIONS[prec]
+    out = torch.empty((n_chains, row_stride(d)), dtype=_state_dtype(p), device=device)
+    _check(lib().laps_philox_normals(seed, n_chains, d, t, tag, substep, p, ctypes.c_void_p(out.data_ptr()),
+                                     _stream_ptr()))
+    return out[:, :d]

@@ -1,0 +1,109 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/laps.h declares, and rejects invalid arguments before it touches a
+device (no compute calls are made here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2601_16696_amd import build, laps
+    if not os.path.exists(laps.LIB_PATH):
+        build.build(verbose=False)
+    return laps
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "laps.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(laps_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert "laps_init" in names and "laps_step_adjusted" in names
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_row_stride_and_defaults(L):
+    assert [L.row_stride(d) for d in (1, 2, 8, 9, 100, 2429)] == [8, 8, 8, 16, 104, 2432]
+    c = L.Config()
+    L.lib().laps_config_default(ctypes.byref(c), 1024, 100)
+    assert (c.C, c.alpha, c.eps0_factor, c.switch_tol, c.window_frac, c.acc_tol) == (0.025, 2.0, 0.01, 0.01, 0.2, 0.03)
+    assert (c.L_partial_factor, c.n_steps_traj, c.eevpd_mode) == (1.25, 15, 1)
+
+
+def _cfg_target(L, kind=0, N=16, d=10, side=0):
+    c = L.Config()
+    L.lib().laps_config_default(ctypes.byref(c), N, d)
+    t = L.TargetS()
+    t.kind = kind
+    t.d = d
+    t.data[0] = 0x1000
+    t.data[1] = 0x2000
+    t.dims[0] = side if side else 7
+    return c, t
+
+
+def _ws(L, c, t):
+    n = ctypes.c_size_t(0)
+    st = L.lib().laps_workspace_size(ctypes.byref(c), ctypes.byref(t), ctypes.byref(n))
+    return st, n.value
+
+
+def test_validation_codes(L):
+    c, t = _cfg_target(L)
+    st, n = _ws(L, c, t)
+    assert st == L.OK and n > 0 and n % 256 == 0
+    c.d = 1
+    t.d = 1
+    assert _ws(L, c, t)[0] == L.EINVAL           # d - 1 divides the velocity update
+    c, t = _cfg_target(L, N=1)
+    assert _ws(L, c, t)[0] == L.EINVAL
+    c, t = _cfg_target(L)
+    t.d = 11
+    assert _ws(L, c, t)[0] == L.EINVAL
+    c, t = _cfg_target(L, kind=3, d=10, side=3)   # 3 x 3 != 10
+    assert _ws(L, c, t)[0] == L.EINVAL
+    c, t = _cfg_target(L, kind=3, d=9, side=3)
+    assert _ws(L, c, t)[0] == L.OK
+    c, t = _cfg_target(L, kind=9)
+    assert _ws(L, c, t)[0] == L.EINVAL
+    c, t = _cfg_target(L)
+    t.data[0] = None
+    assert _ws(L, c, t)[0] == L.EINVAL
+    c, t = _cfg_target(L, d=40000)
+    assert _ws(L, c, t)[0] == L.EUNSUPPORTED
+    c, t = _cfg_target(L)
+    c.eevpd_mode = 3
+    assert _ws(L, c, t)[0] == L.EINVAL
+
+
+def test_init_rejects_before_touching_the_device(L):
+    lib = L.lib()
+    c, t = _cfg_target(L)
+    st, n = _ws(L, c, t)
+    ctx = ctypes.c_void_p()
+    P = ctypes.c_void_p
+    # null positions
+    assert lib.laps_init(ctypes.byref(c), ctypes.byref(t), None, None, P(0x10000), n, None, ctypes.byref(ctx)) == L.EINVAL
+    # misaligned positions / workspace
+    assert lib.laps_init(ctypes.byref(c), ctypes.byref(t), P(0x10004), None, P(0x10000), n, None,
+                         ctypes.byref(ctx)) == L.EINVAL
+    assert lib.laps_init(ctypes.byref(c), ctypes.byref(t), P(0x10000), None, P(0x10040), n, None,
+                         ctypes.byref(ctx)) == L.EINVAL
+    # short workspace
+    assert lib.laps_init(ctypes.byref(c), ctypes.byref(t), P(0x10000), None, P(0x10000), n - 256, None,
+                         ctypes.byref(ctx)) == L.EWORKSPACE
+    assert lib.laps_step_unadjusted(None, 1) == L.EINVAL
+    assert lib.laps_step_adjusted(None, 1) == L.EINVAL
+    assert lib.laps_status_string(L.EPHASE).decode() == "wrong phase"
