@@ -196,6 +196,13 @@ laps_status laps_philox_words(const uint64_t *ctr_dev, uint64_t *out_dev, int64_
 laps_status laps_philox_normals(uint64_t seed, int64_t n_chains, int64_t d, uint64_t t, uint32_t tag,
                                 uint32_t substep, int32_t prec, void *out_dev, void *stream);
 
+/* Times the target gradient of the context (every kernel one ensemble
+ * gradient evaluation takes) at the current positions: n_reps evaluations
+ * enqueued on the context's stream between two HIP events; *avg_ms receives
+ * the mean time of one.  Overwrites only the gradient/log p staging of the
+ * workspace with values at the current positions.  Synchronises the stream. */
+laps_status laps_time_gradient(laps_ctx *ctx, int32_t n_reps, float *avg_ms);
+
 /* Device pointers into the context's workspace: 0 u [N][ld], 1 g [N][ld],
  * 2 logp [N] (double), 3 delta [N] (double), 4 acc [N] (double),
  * 5 sigma [ld] (state type).  NULL for an unknown index. */

@@ -102,7 +102,7 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, Shape &s) {
     if (pb > body) body = pb;
   }
   s.shmem = 2 * kRedSlots * sizeof(double) + body;
-  s.nb = (int)((d + 255) / 256);
+  s.nb = (int)((d + 31) / 32);
   return true;
 }
 
@@ -110,14 +110,17 @@ bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
   const bool dbl = cfg->prec == LAPS_F64;
   if (is_local(tg->kind)) return local_shape(tg->kind, dbl, cfg->n_chains, cfg->d, s);
   if (tg->kind == LAPS_LOGREG) {
-    const int tile = logreg_tile_chains(cfg->prec);
-    s.T = 0;
-    s.Q = 0;
-    s.tpw = tile;
+    const int64_t octs = (cfg->d + 7) / 8;
+    if (cfg->d > 320) return false;
+    int T = 1;
+    while (T < octs) T <<= 1;
+    s.T = T;
+    s.Q = 1;
     s.block = 256;
-    s.G = (int)((cfg->n_chains + tile - 1) / tile);
-    s.shmem = 0;
-    s.nb = (int)((cfg->d + 255) / 256);
+    s.tpw = 256 / T;
+    s.G = (int)((cfg->n_chains + s.tpw - 1) / s.tpw);
+    s.shmem = 2 * kRedSlots * sizeof(double) + (size_t)4 * 8 * T * 8;
+    s.nb = (int)((cfg->d + 31) / 32);
     return true;
   }
   return false;
@@ -162,7 +165,13 @@ Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
   L.part2 = c.take((size_t)s.nb * 4 * 8);
   L.sigma = c.take((size_t)ld * rs);
   L.aux = c.take((size_t)ld * rs);
-  L.packed = c.take(tg->kind == LAPS_LOGREG ? logreg_packed_bytes(cfg->prec, tg->dims[0], d) : 0);
+  size_t lr = 0;
+  if (tg->kind == LAPS_LOGREG) {
+    int S, NB, bps;
+    logreg_splits(tg->dims[0], N, S, NB, bps);
+    lr = logreg_layout(cfg->prec == LAPS_F64 ? 0 : 1, tg->dims[0], d, N, ld, S).total;
+  }
+  L.packed = c.take(lr);
   L.total = (size_t)round_up((int64_t)c.off, 256);
   return L;
 }
@@ -193,6 +202,7 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
       break;
     case LAPS_LOGREG:
       if (!tg->data[0] || !tg->data[1] || tg->dims[0] < 1) return why = "logreg needs X, y and n", LAPS_EINVAL;
+      if (cfg->d > 320) return why = "logistic regression supports d <= 320", LAPS_EUNSUPPORTED;
       break;
     default:
       return why = "unknown target kind", LAPS_EINVAL;
@@ -240,7 +250,7 @@ LocalArgs local_args(laps_ctx *c) {
   return a;
 }
 
-LogregArgs logreg_args(laps_ctx *c) {
+LogregArgs logreg_args(laps_ctx *c, int gate) {
   LogregArgs a{};
   a.x = c->x;
   a.u = c->u;
@@ -254,16 +264,21 @@ LogregArgs logreg_args(laps_ctx *c) {
   a.sigma = c->sigma;
   a.X = c->tg.data[0];
   a.y = static_cast<const double *>(c->tg.data[1]);
-  a.Xt = c->packed;
+  a.scratch = static_cast<char *>(c->packed);
   a.n = c->tg.dims[0];
   a.N = c->cfg.n_chains;
   a.d = c->cfg.d;
   a.ld = c->ld;
-  a.ldX = c->cfg.d;
+  logreg_splits(a.n, a.N, a.S, a.NB, a.bps);
+  a.KC = (int)((a.d + 31) / 32);
+  a.T = c->T;
+  a.tpw = c->tpw;
   a.seed = c->cfg.seed;
   a.max_total = c->cfg.max_steps_total;
   a.n_traj = c->cfg.n_steps_traj;
   a.Lp_factor = c->cfg.L_partial_factor;
+  a.gate = gate;
+  a.integ = c->integ;
   return a;
 }
 
@@ -324,10 +339,36 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
                ? LAPS_OK
                : fail(c, hipGetLastError(), "per-chain kernel");
   }
-  LogregArgs a = logreg_args(c);
-  a.u0 = u0;
-  const hipError_t e = launch_logreg(c->cfg.prec, kk, a, c->G, c->stream);
-  return e == hipSuccess ? LAPS_OK : fail(c, e, "logistic-regression kernel");
+  const int prec = c->cfg.prec;
+  auto upd = [&](LogregArgs &a, int mode, int j, int k) -> hipError_t {
+    a.mode = mode;
+    a.j = j;
+    a.k = k;
+    return launch_logreg_update(prec, a, c->G, c->shmem, c->stream);
+  };
+  hipError_t e = hipSuccess;
+  if (kk == KK_INIT) {
+    LogregArgs a = logreg_args(c, 0);
+    a.u0 = u0;
+    if (prec != LAPS_F64) e = launch_logreg_pack(a, c->stream);
+    if (e == hipSuccess) e = launch_logreg_grad(prec, a, c->stream);
+    if (e == hipSuccess) e = upd(a, LR_INIT, 0, 0);
+  } else if (kk == KK_UNADJ) {
+    LogregArgs a = logreg_args(c, 1);
+    e = upd(a, LR_PRE, 0, 0);
+    if (e == hipSuccess) e = launch_logreg_grad(prec, a, c->stream);
+    if (e == hipSuccess) e = upd(a, LR_POST, 0, 0);
+  } else {
+    LogregArgs a = logreg_args(c, 2);
+    const int K = integrator_coeffs(c->integ).K;
+    e = upd(a, LR_MBEGIN, 0, 0);
+    for (int j = 0; j < c->cfg.n_steps_traj && e == hipSuccess; ++j)
+      for (int k = 0; k < K - 1 && e == hipSuccess; ++k) {
+        e = launch_logreg_grad(prec, a, c->stream);
+        if (e == hipSuccess) e = upd(a, LR_MSTEP, j, k);
+      }
+  }
+  return e == hipSuccess ? LAPS_OK : fail(c, e, "logistic-regression kernels");
 }
 
 }  // namespace
@@ -425,8 +466,6 @@ extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, 
   }
   if (tg->kind == LAPS_GAUSS_DIAG || tg->kind == LAPS_STOCHVOL)
     e = launch_prep_aux(tg->kind, c->dbl, tg->data[0], c->aux, cfg->d, c->ld, c->stream);
-  if (e == hipSuccess && tg->kind == LAPS_LOGREG)
-    e = launch_logreg_pack(cfg->prec, tg->data[0], c->packed, tg->dims[0], cfg->d, c->stream);
   if (e == hipSuccess) e = launch_hyper_init(ca, c->stream);
   if (e != hipSuccess) {
     fail(c, e, "init");
@@ -589,4 +628,32 @@ extern "C" const char *laps_status_string(laps_status s) {
 extern "C" const char *laps_last_error(const laps_ctx *c) {
   if (c && !c->err.empty()) return c->err.c_str();
   return g_last_global.c_str();
+}
+
+extern "C" laps_status laps_time_gradient(laps_ctx *c, int32_t n_reps, float *avg_ms) {
+  if (!c || n_reps < 1 || !avg_ms) return LAPS_EINVAL;
+  hipEvent_t e0, e1;
+  LAPS_CHECK(c, hipEventCreate(&e0), "event");
+  LAPS_CHECK(c, hipEventCreate(&e1), "event");
+  hipError_t e = hipEventRecord(e0, c->stream);
+  for (int32_t k = 0; k < n_reps && e == hipSuccess; ++k) {
+    if (is_local(c->tg.kind)) {
+      LocalArgs a = local_args(c);
+      a.logp_out = c->logp;
+      a.g_out = c->g;
+      e = launch_local(c->tg.kind, c->dbl, c->Q, KK_EVAL, a, c->G, c->block, c->shmem, c->stream);
+    } else {
+      LogregArgs a = logreg_args(c, 0);
+      e = launch_logreg_grad(c->cfg.prec, a, c->stream);
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(c, e, "gradient timing");
+  *avg_ms = ms / (float)n_reps;
+  return LAPS_OK;
 }

@@ -60,30 +60,65 @@ __global__ void k_hyper_init(CtlArgs c) {
   H->switched = 0;
 }
 
-// One thread per dimension.
-__global__ void __launch_bounds__(256) k_finalize(CtlArgs c, int mode) {
+// 32 dimensions per 1024-thread block: lane group rg (0..31) of dimension
+// column dl sums partial rows rg, rg + 32, ...; the 32 group sums are then
+// added in group order, so the result does not depend on timing.  The moving
+// window is reduced the same way over its slots.
+constexpr int kFinDims = 32, kFinGroups = 32;
+
+__device__ __forceinline__ void fin_combine(double (&v)[4], double *sh, int dl, int rg) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sh[(rg * 4 + k) * kFinDims + dl] = v[k];
+  __syncthreads();
+  if (rg == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double s = 0.0;
+      for (int g = 0; g < kFinGroups; ++g) s += sh[(g * 4 + k) * kFinDims + dl];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_finalize(CtlArgs c, int mode) {
   const DevHyper *H = c.hyp;
   if (mode == FIN_UNADJ && H->phase != PH_UNADJ) return;
-  __shared__ double sh[4 * 4];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sh[kFinGroups * 4 * kFinDims];
+  __shared__ double bsh[16 * 4];
+  __shared__ double mu_sh[kFinDims];
+  const int dl = threadIdx.x % kFinDims, rg = threadIdx.x / kFinDims;
+  const int64_t i = (int64_t)blockIdx.x * kFinDims + dl;
   const int64_t d = c.d, ld = c.ld;
-  double Dp = 0.0, vp = 0.0, wd = -INFINITY;
-  if (i < d) {
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-    for (int gI = 0; gI < c.G; ++gI) {
-      const double *P = c.partials + (size_t)gI * 4 * ld;
-      s1 += P[i];
-      s2 += P[ld + i];
-      s3 += P[2 * ld + i];
-      s4 += P[3 * ld + i];
+  const bool act = i < d;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (act) {
+    int gI = rg;
+    for (; gI + 3 * kFinGroups < c.G; gI += 4 * kFinGroups) {
+      const double *P0 = c.partials + (size_t)gI * 4 * ld + i;
+      const double *P1 = P0 + (size_t)kFinGroups * 4 * ld;
+      const double *P2 = P1 + (size_t)kFinGroups * 4 * ld;
+      const double *P3 = P2 + (size_t)kFinGroups * 4 * ld;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += ((P0[k * ld] + P1[k * ld]) + (P2[k * ld] + P3[k * ld]));
     }
+    for (; gI < c.G; gI += kFinGroups) {
+      const double *P = c.partials + (size_t)gI * 4 * ld + i;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += P[k * ld];
+    }
+  }
+  fin_combine(v, sh, dl, rg);
+  double Dp = 0.0, vp = 0.0, wd = -INFINITY;
+  const bool full = mode == FIN_UNADJ && (H->ring_count + 1 >= c.Tw);
+  if (rg == 0 && act) {
     const double invN = 1.0 / (double)c.N;
     const double K = c.shiftK[i];
-    const double m1 = s1 * invN;
+    const double m1 = v[0] * invN;
     const double mean = K + m1;
-    const double var = s2 * invN - m1 * m1;
+    const double var = v[1] * invN - m1 * m1;
     const double m2 = var + mean * mean;
-    const double V = -(s3 * invN - m1 * (s4 * invN));
+    const double V = -(v[2] * invN - m1 * (v[3] * invN));
     c.mean[i] = mean;
     c.var[i] = var;
     c.m2[i] = m2;
@@ -91,32 +126,37 @@ __global__ void __launch_bounds__(256) k_finalize(CtlArgs c, int mode) {
     c.shiftK[i] = mean;
     Dp = (1.0 - V) * (1.0 - V);
     vp = var;
-    if (mode == FIN_UNADJ) {
-      const int64_t pos = H->ring_pos;
-      c.ring[pos * ld + i] = m2;
-      const int64_t cnt = H->ring_count + 1 < c.Tw ? H->ring_count + 1 : c.Tw;
-      if (cnt == c.Tw) {
-        // two-pass mean and sample variance over the window (slot order)
-        double mu = 0.0;
-        for (int64_t k = 0; k < c.Tw; ++k) mu += c.ring[k * ld + i];
-        mu /= (double)c.Tw;
-        double ss = 0.0;
-        for (int64_t k = 0; k < c.Tw; ++k) {
-          const double e = c.ring[k * ld + i] - mu;
-          ss += e * e;
-        }
-        wd = sqrt(ss / (double)(c.Tw - 1)) / mu;
-        c.wdelta[i] = wd;
+    if (mode == FIN_UNADJ) c.ring[H->ring_pos * ld + i] = m2;
+  }
+  if (full) {
+    __syncthreads();  // the new window entry is visible to the whole block
+    // two-pass mean and sample variance over the window slots
+    double w1[4] = {0.0, 0.0, 0.0, 0.0};
+    if (act)
+      for (int64_t k = rg; k < c.Tw; k += kFinGroups) w1[0] += c.ring[k * ld + i];
+    fin_combine(w1, sh, dl, rg);
+    if (rg == 0) mu_sh[dl] = w1[0] / (double)c.Tw;
+    __syncthreads();
+    const double mu = mu_sh[dl];
+    double w2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (act)
+      for (int64_t k = rg; k < c.Tw; k += kFinGroups) {
+        const double e = c.ring[k * ld + i] - mu;
+        w2[0] += e * e;
       }
+    fin_combine(w2, sh, dl, rg);
+    if (rg == 0 && act) {
+      wd = sqrt(w2[0] / (double)(c.Tw - 1)) / mu;
+      c.wdelta[i] = wd;
     }
   }
-  double v[3] = {Dp, vp, wd};
+  double r3[3] = {Dp, vp, wd};
   const int op[3] = {0, 0, 1};
-  block_reduce<3>(v, op, sh);
+  block_reduce<3>(r3, op, bsh);
   if (threadIdx.x == 0) {
-    c.part2[blockIdx.x * 4 + 0] = v[0];
-    c.part2[blockIdx.x * 4 + 1] = v[1];
-    c.part2[blockIdx.x * 4 + 2] = v[2];
+    c.part2[blockIdx.x * 4 + 0] = r3[0];
+    c.part2[blockIdx.x * 4 + 1] = r3[1];
+    c.part2[blockIdx.x * 4 + 2] = r3[2];
   }
 }
 
@@ -129,7 +169,15 @@ __device__ __forceinline__ double F_bias(double D) {
 __device__ __forceinline__ void chain_sums(const double *a, int64_t N, double shiftv, int sq, double &sum,
                                            double &bad, double *sh) {
   double s = 0.0, nb = 0.0;
-  for (int64_t m = threadIdx.x; m < N; m += blockDim.x) {
+  int64_t m = threadIdx.x;
+  const int64_t B = blockDim.x;
+  for (; m + 3 * B < N; m += 4 * B) {
+    const double a0 = a[m], a1 = a[m + B], a2 = a[m + 2 * B], a3 = a[m + 3 * B];
+    const double v0 = a0 - shiftv, v1 = a1 - shiftv, v2 = a2 - shiftv, v3 = a3 - shiftv;
+    s += sq ? ((v0 * v0 + v1 * v1) + (v2 * v2 + v3 * v3)) : ((v0 + v1) + (v2 + v3));
+    nb += (double)(!isfinite(a0)) + (double)(!isfinite(a1)) + (double)(!isfinite(a2)) + (double)(!isfinite(a3));
+  }
+  for (; m < N; m += B) {
     const double v = a[m] - shiftv;
     s += sq ? v * v : v;
     if (!isfinite(a[m])) nb += 1.0;
@@ -152,10 +200,10 @@ __global__ void __launch_bounds__(256) k_ctl_init(CtlArgs c) {
   H->L = c.alpha * sqrt(sv);
 }
 
-__global__ void __launch_bounds__(256) k_ctl_unadj(CtlArgs c) {
+__global__ void __launch_bounds__(1024) k_ctl_unadj(CtlArgs c) {
   DevHyper *H = c.hyp;
   if (H->phase != PH_UNADJ) return;
-  __shared__ double sh[4 * 4];
+  __shared__ double sh[16 * 4];
   __shared__ double mean_sh;
   double sum, bad;
   chain_sums(c.delta, c.N, 0.0, 0, sum, bad, sh);
@@ -228,10 +276,10 @@ __global__ void __launch_bounds__(256) k_switch(CtlArgs c) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_ctl_adj(CtlArgs c) {
+__global__ void __launch_bounds__(1024) k_ctl_adj(CtlArgs c) {
   DevHyper *H = c.hyp;
   if (H->phase != PH_ADJ || H->t >= c.max_total) return;
-  __shared__ double sh[4 * 4];
+  __shared__ double sh[16 * 4];
   double sa, bad0;
   chain_sums(c.acc, c.N, 0.0, 0, sa, bad0, sh);
   double sd, bad;
@@ -263,7 +311,7 @@ hipError_t launch_hyper_init(const CtlArgs &c, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_finalize(const CtlArgs &c, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(c.nb), dim3(256), 0, s, c, mode);
+  hipLaunchKernelGGL(k_finalize, dim3(c.nb), dim3(1024), 0, s, c, mode);
   return hipGetLastError();
 }
 hipError_t launch_ctl_init(const CtlArgs &c, hipStream_t s) {
@@ -271,7 +319,7 @@ hipError_t launch_ctl_init(const CtlArgs &c, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_unadj, dim3(1), dim3(256), 0, s, c);
+  hipLaunchKernelGGL(k_ctl_unadj, dim3(1), dim3(1024), 0, s, c);
   return hipGetLastError();
 }
 hipError_t launch_switch(const CtlArgs &c, hipStream_t s) {
@@ -279,7 +327,7 @@ hipError_t launch_switch(const CtlArgs &c, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_ctl_adj(const CtlArgs &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_adj, dim3(1), dim3(256), 0, s, c);
+  hipLaunchKernelGGL(k_ctl_adj, dim3(1), dim3(1024), 0, s, c);
   return hipGetLastError();
 }
 

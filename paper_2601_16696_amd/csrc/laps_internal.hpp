@@ -71,7 +71,9 @@ hipError_t launch_local(int kind, bool dbl, int Q, KernelKind kk, const LocalArg
                         size_t shmem, hipStream_t s);
 hipError_t launch_prep_aux(int kind, bool dbl, const void *src, void *aux, int64_t d, int64_t ld, hipStream_t s);
 
-// Logistic regression.
+// Logistic regression.  The gradient kernels split the n data rows over S
+// workgroup columns and write per-split partial sums (G = X^T r rows and
+// sum_n [y z - softplus z]); the per-chain update kernels combine them.
 struct LogregArgs {
   void *x, *u, *g;
   double *logp, *delta, *acc, *partials;
@@ -79,20 +81,56 @@ struct LogregArgs {
   DevHyper *hyp;
   const void *sigma;
   const void *u0;
-  const void *X;           // [n][d] (double for F64, bf16 bits for F32/mixed)
-  const double *y;         // [n]
-  const void *Xt;          // packed operand (bf16 paths)
-  int64_t n, N, d, ld, ldX;
+  const void *X;           // LAPS_F64: double [n][d]; bf16 paths: uint16 bf16 bits [n][d]
+  const double *y;         // [n] labels
+  char *scratch;           // region laid out by logreg_layout()
+  int64_t n, N, d, ld;
+  int S, NB, KC, bps;      // row splits, 32-row blocks, 32-wide k chunks, blocks per split
+  int T, tpw;              // team shape of the update kernels
   uint64_t seed;
   int64_t max_total;
   int n_traj;
   double Lp_factor;
-  double *logp_out;
-  void *g_out;
+  int gate;                // 0: always; 1: unadjusted phase; 2: adjusted phase below max_total
+  int mode, j, k, integ;   // update-kernel selector
 };
-hipError_t launch_logreg(int prec, KernelKind kk, const LogregArgs &a, int grid, hipStream_t s);
-int logreg_tile_chains(int prec);
-size_t logreg_packed_bytes(int prec, int64_t n, int64_t d);
-hipError_t launch_logreg_pack(int prec, const void *X, void *Xt, int64_t n, int64_t d, hipStream_t s);
+
+enum { LR_INIT = 0, LR_PRE = 1, LR_POST = 2, LR_MBEGIN = 3, LR_MSTEP = 4 };
+
+struct LrOffsets {
+  size_t Xf, Xb, yf, Gp, lp, x0, g0, sc, total;
+};
+__host__ __device__ inline size_t lr_al256(size_t v) { return (v + 255) / 256 * 256; }
+
+__host__ __device__ inline LrOffsets logreg_layout(int prec, int64_t n, int64_t d, int64_t N, int64_t ld, int S) {
+  const int64_t NB = (n + 31) / 32, KC = (d + 31) / 32;
+  const size_t rs = prec == 0 ? 8 : 4;
+  const bool bf = prec != 0;
+  LrOffsets o{};
+  size_t off = 0;
+  o.Xf = off;
+  off = lr_al256(off + (bf ? (size_t)NB * 2 * KC * 64 * 8 * 2 : 0));
+  o.Xb = off;
+  off = lr_al256(off + (bf ? (size_t)NB * 2 * KC * 64 * 8 * 2 : 0));
+  o.yf = off;
+  off = lr_al256(off + (bf ? (size_t)NB * 32 * 4 : 0));
+  o.Gp = off;
+  off = lr_al256(off + (size_t)S * N * ld * rs);
+  o.lp = off;
+  off = lr_al256(off + (size_t)S * N * 8);
+  o.x0 = off;
+  off = lr_al256(off + (size_t)N * ld * rs);
+  o.g0 = off;
+  off = lr_al256(off + (size_t)N * ld * rs);
+  o.sc = off;
+  off = lr_al256(off + (size_t)4 * N * 8);
+  o.total = off;
+  return o;
+}
+
+void logreg_splits(int64_t n, int64_t N, int &S, int &NB, int &bps);
+hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s);
+hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s);
+hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, size_t shmem, hipStream_t s);
 
 }  // namespace laps

@@ -9,94 +9,9 @@
 // products are team reductions; per-dimension ensemble sums are accumulated in
 // registers across all chains a workgroup visits and written once per
 // workgroup as FP64 partial rows.
-#include "laps_internal.hpp"
+#include "laps_team.hpp"
 
 namespace laps {
-
-// ---------------------------------------------------------------------------
-// register-tile helpers
-// ---------------------------------------------------------------------------
-template <class Real, int Q>
-struct Tile {
-  Real v[Q][8];
-};
-
-template <class Real>
-__device__ __forceinline__ void ld8(const Real *p, Real (&v)[8]);
-template <>
-__device__ __forceinline__ void ld8<float>(const float *p, float (&v)[8]) {
-  const float4 a = *reinterpret_cast<const float4 *>(p);
-  const float4 b = *reinterpret_cast<const float4 *>(p + 4);
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-template <>
-__device__ __forceinline__ void ld8<double>(const double *p, double (&v)[8]) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double2 a = *reinterpret_cast<const double2 *>(p + 2 * k);
-    v[2 * k] = a.x;
-    v[2 * k + 1] = a.y;
-  }
-}
-template <class Real>
-__device__ __forceinline__ void st8(Real *p, const Real (&v)[8]);
-template <>
-__device__ __forceinline__ void st8<float>(float *p, const float (&v)[8]) {
-  *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
-  *reinterpret_cast<float4 *>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
-}
-template <>
-__device__ __forceinline__ void st8<double>(double *p, const double (&v)[8]) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) *reinterpret_cast<double2 *>(p + 2 * k) = make_double2(v[2 * k], v[2 * k + 1]);
-}
-
-// Loads the lane's octs of one row; coordinates >= d read as zero.
-template <class Real, int Q>
-__device__ __forceinline__ void load_row(const Real *row, int r, int T, int64_t d, bool act, Real (&v)[Q][8]) {
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t e0 = 8 * (int64_t)(r + q * T);
-    if (act && e0 < d) {
-      ld8<Real>(row + e0, v[q]);
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (e0 + i >= d) v[q][i] = Real(0);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[q][i] = Real(0);
-    }
-  }
-}
-
-template <class Real, int Q>
-__device__ __forceinline__ void store_row(Real *row, int r, int T, int64_t d, const Real (&v)[Q][8]) {
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t e0 = 8 * (int64_t)(r + q * T);
-    if (e0 < d) st8<Real>(row + e0, v[q]);
-  }
-}
-
-// Standard normals for the lane's octs (zero beyond d).
-template <class Real, int Q>
-__device__ __forceinline__ void lane_normals(uint64_t seed, uint64_t m, int r, int T, int64_t d, uint64_t t,
-                                             uint32_t tag, uint32_t sub, Real (&z)[Q][8]) {
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t oct = r + q * T;
-    if (8 * oct < d) {
-      normals8<Real>(seed, m, (uint64_t)oct, t, tag, sub, z[q]);
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (8 * oct + i >= d) z[q][i] = Real(0);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) z[q][i] = Real(0);
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Targets.  eval() returns this lane's share of log p (the caller reduces it
@@ -282,94 +197,6 @@ struct SVTgt {
   const int64_t N = a.N, d = a.d, ld = a.ld;                                                \
   const double dm1 = (double)(d - 1);
 
-// Per-dimension sums over every chain this workgroup visited, written as one
-// partial row per workgroup: teams inside a wavefront are combined by xor
-// butterflies, wavefronts in a fixed order through LDS.
-template <class Real, int Q>
-__device__ __forceinline__ void write_partials(const LocalArgs &a, double (&S)[4][Q][8], double *red, int T, int r) {
-  const int64_t d = a.d, ld = a.ld;
-  double *P = a.partials + (size_t)blockIdx.x * 4 * ld;
-  if ((int)blockDim.x == T) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int64_t e0 = 8 * (int64_t)(r + q * T);
-        if (e0 < d)
-#pragma unroll
-          for (int i = 0; i < 8; ++i) P[k * ld + e0 + i] = S[k][q][i];
-      }
-    return;
-  }
-  // T < blockDim: first fold teams that share a wavefront
-  for (int msk = T; msk < 64; msk <<= 1) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) S[k][q][i] += __shfl_xor(S[k][q][i], msk);
-  }
-  // then wavefront (or multi-wave team) groups in order, accumulated in LDS
-  const int lanes = T;  // lanes holding a distinct set of dims
-  const int groups = blockDim.x / (T < 64 ? 64 : T);
-  const int grp = threadIdx.x / (T < 64 ? 64 : T);
-  const int lig = threadIdx.x - grp * (T < 64 ? 64 : T);  // lane index inside its group
-  double *buf = red + 2 * kRedSlots;                       // after the reduction slots
-  const int span = 8 * Q * lanes;
-  for (int gI = 0; gI < groups; ++gI) {
-    if (grp == gI && lig < lanes) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int idx = k * span + (q * lanes + lig) * 8 + i;
-            buf[idx] = (gI == 0 ? 0.0 : buf[idx]) + S[k][q][i];
-          }
-    }
-    __syncthreads();
-  }
-  if (grp == 0 && lig < lanes) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int64_t e0 = 8 * (int64_t)(r + q * T);
-        if (e0 < d)
-#pragma unroll
-          for (int i = 0; i < 8; ++i) P[k * ld + e0 + i] = buf[k * span + (q * lanes + lig) * 8 + i];
-      }
-  }
-}
-
-template <class Real, int Q>
-__device__ __forceinline__ void accumulate_stats(double (&S)[4][Q][8], const double (&K)[Q][8],
-                                                 const Real (&x)[Q][8], const Real (&g)[Q][8]) {
-#pragma unroll
-  for (int q = 0; q < Q; ++q)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const double dx = (double)x[q][i] - K[q][i];
-      const double gv = (double)g[q][i];
-      S[0][q][i] += dx;
-      S[1][q][i] += dx * dx;
-      S[2][q][i] += dx * gv;
-      S[3][q][i] += gv;
-    }
-}
-
-template <int Q>
-__device__ __forceinline__ void load_shift(const double *K, int r, int T, int64_t d, double (&v)[Q][8]) {
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int64_t e0 = 8 * (int64_t)(r + q * T);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[q][i] = (e0 + i < d) ? K[e0 + i] : 0.0;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Initialisation: log p and gradient at x, u = g/|g| (u0 if given; a uniform
 // random direction when the gradient vanishes), per-dim sums for the initial
@@ -422,7 +249,7 @@ __global__ void __launch_bounds__(512) k_init(LocalArgs a) {
       accumulate_stats<Real, Q>(S, K0, x, g);
     }
   }
-  write_partials<Real, Q>(a, S, red, T, r);
+  write_partials<Real, Q>(a.partials, a.d, a.ld, S, red, T, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -520,7 +347,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
       accumulate_stats<Real, Q>(S, K, x, g);
     }
   }
-  write_partials<Real, Q>(a, S, red, T, r);
+  write_partials<Real, Q>(a.partials, a.d, a.ld, S, red, T, r);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,9 +1,812 @@
-// Logistic regression target (placeholder until the matrix-core kernels land).
-#include "laps_internal.hpp"
+// Bayesian logistic regression target of the LAPS hot path.
+//
+// Gradient: for chain positions theta (rows of x), z = X theta over the n data
+// rows, r = y - sigmoid(z), grad log p = X^T r - theta and
+// log p = sum_n [y z - softplus(z)] - |theta|^2 / 2.
+//
+// Mixed precision (LAPS_MIXED_BF16): both contractions run on bf16 matrix
+// cores (v_mfma_f32_16x16x32_bf16) with float accumulation, fused so z never
+// leaves registers: a wavefront holds 16 chains; per 32-row block of X it
+// computes z^T (rows x chains) with theta split into bf16 hi + lo parts (X is
+// exactly bf16 by construction, so z carries ~2^-17 relative error), applies
+// the sigmoid/softplus epilogue in float (log p terms summed in double), and
+// accumulates G^T += X^T r^T from the epilogue registers directly: the K
+// index of the second product is permuted to the first product's output
+// layout, and both operands of X are pre-packed in fragment order.  The n
+// rows are split over S workgroup columns; per-split partial sums are
+// combined by the per-chain update kernels.
+//
+// Plain FP64 (LAPS_F64): the same partial-sum interface with a double-precision
+// vector-ALU gradient (the baseline the mixed path is measured against).
+#include "laps_team.hpp"
 
 namespace laps {
-int logreg_tile_chains(int) { return 64; }
-size_t logreg_packed_bytes(int, int64_t, int64_t) { return 0; }
-hipError_t launch_logreg_pack(int, const void *, void *, int64_t, int64_t, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_logreg(int, KernelKind, const LogregArgs &, int, hipStream_t) { return hipErrorNotSupported; }
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+void logreg_splits(int64_t n, int64_t N, int &S, int &NB, int &bps) {
+  NB = (int)((n + 31) / 32);
+  const int64_t groups = (N + 63) / 64;
+  int64_t want = 256 / (groups > 0 ? groups : 1);
+  if (want < 1) want = 1;
+  if (want > NB) want = NB;
+  bps = (int)((NB + want - 1) / want);
+  S = (NB + bps - 1) / bps;
+}
+
+__device__ __forceinline__ bool lr_gate(const LogregArgs &a) {
+  if (a.gate == 0) return true;
+  const DevHyper *H = a.hyp;
+  if (a.gate == 1) return H->phase == PH_UNADJ;
+  return H->phase == PH_ADJ && H->t < a.max_total;
+}
+
+// ---------------------------------------------------------------------------
+// operand packing (bf16 paths), once per context
+//   Xf[b][h][kc][lane][j] = X[32b + 16h + lane%16][32kc + 16(j/4) + 4(lane/16) + j%4]
+//   Xb[b][dc][lane][j]    = X[32b + 16(j/4) + 4(lane/16) + j%4][16dc + lane%16]
+//   yf[row]               = y[row] (0 beyond n)
+// ---------------------------------------------------------------------------
+__global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, int64_t d, int KC, int NB,
+                          unsigned short *Xf, unsigned short *Xb, float *yf) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nf = (int64_t)NB * 2 * KC * 64;
+  if (tid < nf) {
+    const int lane = (int)(tid % 64);
+    const int64_t rest = tid / 64;
+    const int kc = (int)(rest % KC);
+    const int h = (int)((rest / KC) % 2);
+    const int64_t b = rest / (2 * KC);
+    const int64_t row = 32 * b + 16 * h + (lane & 15);
+    for (int j = 0; j < 8; ++j) {
+      const int64_t col = 32 * kc + 16 * (j >> 2) + 4 * (lane >> 4) + (j & 3);
+      Xf[tid * 8 + j] = (row < n && col < d) ? X[row * d + col] : (unsigned short)0;
+    }
+    return;
+  }
+  const int64_t t2 = tid - nf;
+  const int64_t nbk = (int64_t)NB * 2 * KC * 64;
+  if (t2 < nbk) {
+    const int lane = (int)(t2 % 64);
+    const int64_t rest = t2 / 64;
+    const int dc = (int)(rest % (2 * KC));
+    const int64_t b = rest / (2 * KC);
+    const int64_t col = 16 * dc + (lane & 15);
+    for (int j = 0; j < 8; ++j) {
+      const int64_t row = 32 * b + 16 * (j >> 2) + 4 * (lane >> 4) + (j & 3);
+      Xb[t2 * 8 + j] = (row < n && col < d) ? X[row * d + col] : (unsigned short)0;
+    }
+    return;
+  }
+  const int64_t t3 = t2 - nbk;
+  if (t3 < (int64_t)NB * 32) yf[t3] = t3 < n ? (float)y[t3] : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// bf16 matrix-core gradient, LDS-staged (d <= 128).  grid (ceil(N/64), S),
+// 512 threads = 8 wavefronts: wavefront w owns chain group w % 4 (16 chains)
+// and row half w / 4 of the split's 32-row blocks (half 0 takes even blocks,
+// half 1 odd ones).  Each iteration stages the operand fragments of two
+// blocks (one per half) in LDS once for all four chain groups; the next two
+// blocks are prefetched into registers while the current ones are computed.
+// The two halves' G and log p partials are added in LDS at the end.
+// ---------------------------------------------------------------------------
+template <int KC, bool FULL>
+__device__ __forceinline__ void lr_block(const bf16x8 *L, const float *Y, int lane, int q, int nvalid,
+                                         const bf16x8 (&thi)[KC], const bf16x8 (&tlo)[KC], f32x4 (&gacc)[2 * KC],
+                                         double &lacc) {
+  // all forward fragments first (one LDS wait), then four independent
+  // accumulation chains: (half 0, half 1) x (theta hi, theta lo)
+  bf16x8 af[2][KC];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) af[h][kc] = L[(h * KC + kc) * 64 + lane];
+  f32x4 zh[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+  f32x4 zl[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      zh[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h][kc], thi[kc], zh[h], 0, 0, 0);
+      zl[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h][kc], tlo[kc], zl[h], 0, 0, 0);
+    }
+  bf16x8 bfr[2 * KC];
+#pragma unroll
+  for (int dc = 0; dc < 2 * KC; ++dc) bfr[dc] = L[2 * KC * 64 + dc * 64 + lane];
+  const float4 y0 = *reinterpret_cast<const float4 *>(Y + 4 * q);
+  const float4 y1 = *reinterpret_cast<const float4 *>(Y + 16 + 4 * q);
+  const float yv[2][4] = {{y0.x, y0.y, y0.z, y0.w}, {y1.x, y1.y, y1.z, y1.w}};
+  // epilogue: r = y - sigmoid(z); log p terms y z - softplus(z), where the
+  // eight log(1 + e^{-|z|}) of the lane are taken as one log of their product
+  // (each factor lies in (1, 2])
+  bf16x8 rb;
+  float lin = 0.f, prod = 1.f;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float zz = zh[h][i] + zl[h][i];
+      const bool ok = FULL || (16 * h + 4 * q + i < nvalid);
+      const float e = ok ? __expf(-fabsf(zz)) : 0.f;
+      const float ope = 1.0f + e;
+      const float inv = __builtin_amdgcn_rcpf(ope);
+      const float sig = zz >= 0.f ? inv : e * inv;
+      rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - sig : 0.f);
+      lin += ok ? yv[h][i] * zz - fmaxf(zz, 0.f) : 0.f;
+      prod *= ope;
+    }
+  lacc += (double)lin - (double)__logf(prod);
+#pragma unroll
+  for (int dc = 0; dc < 2 * KC; ++dc) gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[dc], rb, gacc[dc], 0, 0, 0);
+}
+
+template <int KC>
+__global__ void __launch_bounds__(512) k_lr_grad_bf16(LogregArgs a) {
+  if (!lr_gate(a)) return;
+  constexpr int kFrag = 4 * KC * 64;      // 16-byte fragments per 32-row block
+  constexpr int kPer = 2 * kFrag / 512;    // staging loads per thread per iteration
+  constexpr int kBuf = 2 * kFrag + 16;     // one buffer: two blocks' fragments + their 2 x 32 labels
+  extern __shared__ bf16x8 lds[];          // [2 buffers][kBuf]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int cg = wave & 3, rh = wave >> 2;
+  const int q = lane >> 4, cl = lane & 15;
+  const int64_t N = a.N, ld = a.ld, n = a.n;
+  const int64_t m = ((int64_t)blockIdx.x * 4 + cg) * 16 + cl;
+  const bool mval = m < N;
+  const float *X = static_cast<const float *>(a.x);
+  bf16x8 thi[KC], tlo[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (mval && d4 < ld) v = *reinterpret_cast<const float4 *>(X + m * ld + d4);
+      const float f[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const __bf16 hi = (__bf16)f[i];
+        thi[kc][4 * hh + i] = hi;
+        tlo[kc][4 * hh + i] = (__bf16)(f[i] - (float)hi);
+      }
+    }
+  }
+  f32x4 gacc[2 * KC];
+#pragma unroll
+  for (int dc = 0; dc < 2 * KC; ++dc) gacc[dc] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double lacc = 0.0;
+  const LrOffsets off = logreg_layout(1, n, a.d, N, ld, a.S);
+  const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
+  const bf16x8 *XB = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xb);
+  const bf16x8 *YF = reinterpret_cast<const bf16x8 *>(a.scratch + off.yf);  // labels, 4 floats per 16 bytes
+  const int s = blockIdx.y;
+  const int b0 = s * a.bps;
+  const int b1 = (b0 + a.bps < a.NB) ? b0 + a.bps : a.NB;
+  const int nit = (b1 - b0 + 1) / 2;
+  // fragment c of an iteration: half c / kFrag; inside a block the forward
+  // fragments (2 KC x 64) precede the backward ones (2 KC x 64); lanes 0..15
+  // also stage the two blocks' labels (8 x 16 bytes each)
+  auto fetch = [&](int it, bf16x8 (&reg)[kPer], bf16x8 &ry) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int c = tid + 512 * k;
+      const int half = c / kFrag, f = c - half * kFrag;
+      const int64_t blk = b0 + 2 * it + half;
+      if (blk < b1)
+        reg[k] = f < 2 * KC * 64 ? XF[blk * 2 * KC * 64 + f] : XB[blk * 2 * KC * 64 + (f - 2 * KC * 64)];
+    }
+    if (tid < 16) {
+      const int64_t blk = b0 + 2 * it + (tid >> 3);
+      if (blk < b1) ry = YF[blk * 8 + (tid & 7)];
+    }
+  };
+  auto stash = [&](int buf, const bf16x8 (&reg)[kPer], const bf16x8 &ry) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) lds[buf * kBuf + tid + 512 * k] = reg[k];
+    if (tid < 16) lds[buf * kBuf + 2 * kFrag + tid] = ry;
+  };
+  bf16x8 reg[kPer], ry;
+  fetch(0, reg, ry);
+  stash(0, reg, ry);
+  __syncthreads();
+  for (int it = 0; it < nit; ++it) {
+    const bool more = it + 1 < nit;
+    if (more) fetch(it + 1, reg, ry);
+    const int64_t blk = b0 + 2 * it + rh;
+    if (blk < b1) {
+      const bf16x8 *L = lds + (it & 1) * kBuf + rh * kFrag;
+      const float *Y = reinterpret_cast<const float *>(lds + (it & 1) * kBuf + 2 * kFrag + 8 * rh);
+      const int64_t nv = n - 32 * blk;
+      if (nv >= 32)
+        lr_block<KC, true>(L, Y, lane, q, 32, thi, tlo, gacc, lacc);
+      else
+        lr_block<KC, false>(L, Y, lane, q, (int)nv, thi, tlo, gacc, lacc);
+    }
+    if (more) stash((it + 1) & 1, reg, ry);
+    __syncthreads();
+  }
+  // half 1 hands its partial sums to half 0 through LDS (fixed order: half 0 + half 1)
+  float *red = reinterpret_cast<float *>(lds);
+  double *lred = reinterpret_cast<double *>(red + 4 * 64 * 8 * KC);
+  if (rh == 1) {
+#pragma unroll
+    for (int dc = 0; dc < 2 * KC; ++dc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[((cg * 2 * KC + dc) * 4 + i) * 64 + lane] = gacc[dc][i];
+    lred[cg * 64 + lane] = lacc;
+  }
+  __syncthreads();
+  if (rh == 0) {
+    float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
+    if (mval) {
+#pragma unroll
+      for (int dc = 0; dc < 2 * KC; ++dc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t dd = 16 * dc + 4 * q + i;
+          if (dd < ld) Gp[dd] = gacc[dc][i] + red[((cg * 2 * KC + dc) * 4 + i) * 64 + lane];
+        }
+    }
+    lacc += lred[cg * 64 + lane];
+    lacc += __shfl_xor(lacc, 16);
+    lacc += __shfl_xor(lacc, 32);
+    if (mval && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// bf16 matrix-core gradient, direct-load variant for d > 128 (fragments
+// from L1/L2).  grid (ceil(N/64), S), 256 threads: wavefront w of workgroup
+// (gx, s) owns chains 64 gx + 16 w .. +15 and data blocks [s bps, (s+1) bps).
+// ---------------------------------------------------------------------------
+template <int KC>
+__global__ void __launch_bounds__(256) k_lr_grad_bf16_direct(LogregArgs a) {
+  if (!lr_gate(a)) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, cl = lane & 15;
+  const int64_t N = a.N, ld = a.ld;
+  const int64_t m = ((int64_t)blockIdx.x * 4 + wave) * 16 + cl;
+  const bool mval = m < N;
+  const float *X = static_cast<const float *>(a.x);
+  // theta as the B operand: k slot 8q + j of chunk kc is coordinate 32kc + 16(j/4) + 4q + j%4
+  bf16x8 thi[KC], tlo[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (mval && d4 < ld) v = *reinterpret_cast<const float4 *>(X + m * ld + d4);
+      const float f[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const __bf16 hi = (__bf16)f[i];
+        thi[kc][4 * hh + i] = hi;
+        tlo[kc][4 * hh + i] = (__bf16)(f[i] - (float)hi);
+      }
+    }
+  }
+  f32x4 gacc[2 * KC];
+#pragma unroll
+  for (int dc = 0; dc < 2 * KC; ++dc) gacc[dc] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double lacc = 0.0;
+  const LrOffsets off = logreg_layout(1, a.n, a.d, N, ld, a.S);
+  const bf16x8 *Xb = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xb);
+  const float *yf = reinterpret_cast<const float *>(a.scratch + off.yf);
+  const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
+  const int s = blockIdx.y;
+  const int b0 = s * a.bps;
+  const int b1 = (b0 + a.bps < a.NB) ? b0 + a.bps : a.NB;
+  const int64_t n = a.n;
+  for (int b = b0; b < b1; ++b) {
+    f32x4 z[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const bf16x8 af = XF[(((int64_t)b * 2 + h) * KC + kc) * 64 + lane];
+        z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, thi[kc], z[h], 0, 0, 0);
+        z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, tlo[kc], z[h], 0, 0, 0);
+      }
+    // epilogue: r = y - sigmoid(z), log p terms y z - softplus(z)
+    bf16x8 rb;
+    float lsum = 0.f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = 32 * (int64_t)b + 16 * h + 4 * q + i;
+        const float zz = z[h][i];
+        const float yv = yf[row];
+        const float e = __expf(-fabsf(zz));
+        const float ope = 1.0f + e;
+        const float inv = __builtin_amdgcn_rcpf(ope);
+        const float sig = zz >= 0.f ? inv : e * inv;
+        const float sp = fmaxf(zz, 0.f) + __logf(ope);
+        const bool ok = row < n;
+        rb[4 * h + i] = (__bf16)(ok ? yv - sig : 0.f);
+        lsum += ok ? yv * zz - sp : 0.f;
+      }
+    lacc += (double)lsum;
+#pragma unroll
+    for (int dc = 0; dc < 2 * KC; ++dc) {
+      const bf16x8 ab = Xb[((int64_t)b * 2 * KC + dc) * 64 + lane];
+      gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, rb, gacc[dc], 0, 0, 0);
+    }
+  }
+  float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
+  if (mval) {
+#pragma unroll
+    for (int dc = 0; dc < 2 * KC; ++dc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t dd = 16 * dc + 4 * q + i;
+        if (dd < ld) Gp[dd] = gacc[dc][i];
+      }
+  }
+  lacc += __shfl_xor(lacc, 16);
+  lacc += __shfl_xor(lacc, 32);
+  if (mval && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
+}
+
+// ---------------------------------------------------------------------------
+// plain FP64 gradient.  grid (ceil(N/16), S), 256 threads, dynamic LDS holds
+// the 16 chains' theta and a 16 x 64 block of residuals.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_lr_grad_f64(LogregArgs a) {
+  if (!lr_gate(a)) return;
+  extern __shared__ double sm[];
+  const int64_t N = a.N, ld = a.ld, d = a.d, n = a.n;
+  double *th = sm;               // [16][ld]
+  double *R = sm + 16 * ld;      // [16][64]
+  const int tid = threadIdx.x;
+  const int64_t m0 = (int64_t)blockIdx.x * 16;
+  const double *x = static_cast<const double *>(a.x);
+  const double *X = static_cast<const double *>(a.X);
+  for (int64_t i = tid; i < 16 * ld; i += 256) {
+    const int64_t c = i / ld, e = i - c * ld;
+    th[i] = (m0 + c < N && e < d) ? x[(m0 + c) * ld + e] : 0.0;
+  }
+  const int s = blockIdx.y;
+  const int64_t r0 = (int64_t)s * a.bps * 32;
+  int64_t r1 = r0 + (int64_t)a.bps * 32;
+  if (r1 > n) r1 = n;
+  // phase-1 role: one row, four chains; phase-2 role: one chain, coordinates dslot + 16k
+  const int prow = tid & 63, pc = (tid >> 6) * 4;
+  const int gc = tid >> 4, dslot = tid & 15;
+  const int kd = (int)((d + 15) / 16);
+  double G[20];
+#pragma unroll
+  for (int k = 0; k < 20; ++k) G[k] = 0.0;
+  double lacc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t rb = r0; rb < r1; rb += 64) {
+    __syncthreads();
+    const int64_t row = rb + prow;
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    if (row < r1) {
+      const double *xr = X + row * d;
+      for (int64_t e = 0; e < d; ++e) {
+        const double xv = xr[e];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) z[c] += xv * th[(pc + c) * ld + e];
+      }
+    }
+    const double yv = row < r1 ? a.y[row] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double rr = 0.0;
+      if (row < r1) {
+        const double ez = exp(-fabs(z[c]));
+        const double sig = z[c] >= 0.0 ? 1.0 / (1.0 + ez) : ez / (1.0 + ez);
+        rr = yv - sig;
+        lacc[c] += yv * z[c] - (fmax(z[c], 0.0) + log1p(ez));
+      }
+      R[(pc + c) * 64 + prow] = rr;
+    }
+    __syncthreads();
+    const int64_t cnt = (r1 - rb) < 64 ? (r1 - rb) : 64;
+    for (int64_t rr = 0; rr < cnt; ++rr) {
+      const double rv = R[gc * 64 + rr];
+      const double *xr = X + (rb + rr) * d;
+#pragma unroll
+      for (int k = 0; k < 20; ++k) {
+        const int64_t e = dslot + 16 * k;
+        if (k < kd && e < d) G[k] += rv * xr[e];
+      }
+    }
+  }
+  const LrOffsets off = logreg_layout(0, n, d, N, ld, a.S);
+  double *Gp = reinterpret_cast<double *>(a.scratch + off.Gp);
+  if (m0 + gc < N) {
+#pragma unroll
+    for (int k = 0; k < 20; ++k) {
+      const int64_t e = dslot + 16 * k;
+      if (k < kd && e < ld) Gp[((int64_t)s * N + m0 + gc) * ld + e] = G[k];
+    }
+  }
+  // log p partials: the 64 lanes of a wavefront share the same four chains
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int msk = 32; msk >= 1; msk >>= 1) lacc[c] += __shfl_xor(lacc[c], msk);
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (m0 + pc + c < N) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m0 + pc + c] = lacc[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-chain update kernels (one team of T <= 64 lanes per chain, 256 threads)
+// ---------------------------------------------------------------------------
+template <class Real>
+__device__ __forceinline__ void lr_grad_sum(const LogregArgs &a, const LrOffsets &off, int64_t m, int r, int T,
+                                            bool act, const Real (&x)[1][8], Real (&g)[1][8], double &lps) {
+  const Real *Gp = reinterpret_cast<const Real *>(a.scratch + off.Gp);
+  const double *lp = reinterpret_cast<const double *>(a.scratch + off.lp);
+  const int64_t e0 = 8 * (int64_t)r;
+  Real acc[8] = {};
+  if (act && e0 < a.d) {
+    for (int s = 0; s < a.S; ++s) {
+      Real v[8];
+      ld8<Real>(Gp + ((int64_t)s * a.N + m) * a.ld + e0, v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] += v[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) g[0][i] = (e0 + i < a.d) ? acc[i] - x[0][i] : Real(0);
+  lps = 0.0;
+  if (act)
+    for (int s = 0; s < a.S; ++s) lps += lp[(int64_t)s * a.N + m];
+}
+
+template <class Real>
+__global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
+  if (!lr_gate(a)) return;
+  extern __shared__ double smem[];
+  double *red = smem;
+  const int T = a.T;
+  const int team = threadIdx.x / T, r = threadIdx.x - team * T;
+  int slot = 0;
+  const int64_t N = a.N, d = a.d, ld = a.ld;
+  const int64_t m = (int64_t)blockIdx.x * a.tpw + team;
+  const bool act = m < N;
+  const double dm1 = (double)(d - 1);
+  const LrOffsets off = logreg_layout(sizeof(Real) == 8 ? 0 : 1, a.n, d, N, ld, a.S);
+  double *sc = reinterpret_cast<double *>(a.scratch + off.sc);
+  double *sc_l0 = sc, *sc_lprev = sc + N, *sc_D = sc + 2 * N, *sc_dk = sc + 3 * N;
+  Real *X = static_cast<Real *>(a.x);
+  Real *U = static_cast<Real *>(a.u);
+  Real *Gc = static_cast<Real *>(a.g);
+  Real *X0 = reinterpret_cast<Real *>(a.scratch + off.x0);
+  Real *G0 = reinterpret_cast<Real *>(a.scratch + off.g0);
+  const DevHyper *H = a.hyp;
+  const double eps = H->eps;
+  const uint64_t t = (uint64_t)H->t;
+  const double h = 0.5 * eps;
+  Real x[1][8], u[1][8], g[1][8], z[1][8];
+  load_row<Real, 1>(X + m * ld, r, T, d, act, x);
+  const int mode = a.mode;
+
+  if (mode == LR_INIT || mode == LR_POST) {
+    double S[4][1][8] = {};
+    double lps;
+    lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
+    if (mode == LR_INIT) {
+      lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, 0, TAG_INIT_DIR, 0, z);
+      double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        v[0] += (double)x[0][i] * (double)x[0][i];
+        v[1] += (double)g[0][i] * (double)g[0][i];
+        v[2] += (double)z[0][i] * (double)z[0][i];
+      }
+      team_sum<3>(v, T, red, slot);
+      const double l1 = lps - 0.5 * v[0];
+      if (a.u0) {
+        load_row<Real, 1>(static_cast<const Real *>(a.u0) + m * ld, r, T, d, act, u);
+      } else {
+        const double gn = sqrt(v[1]);
+        const bool useg = gn > 0.0 && isfinite(gn);
+        const Real scl = (Real)(1.0 / (useg ? gn : sqrt(v[2])));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) u[0][i] = (useg ? g[0][i] : z[0][i]) * scl;
+      }
+      if (act) {
+        store_row<Real, 1>(X + m * ld, r, T, d, x);
+        store_row<Real, 1>(U + m * ld, r, T, d, u);
+        store_row<Real, 1>(Gc + m * ld, r, T, d, g);
+        if (r == 0) {
+          a.logp[m] = l1;
+          a.delta[m] = 0.0;
+          a.acc[m] = 0.0;
+        }
+        const double K0[1][8] = {};
+        accumulate_stats<Real, 1>(S, K0, x, g);
+      }
+    } else {
+      const double Lm = H->L;
+      const Real c1 = (Real)exp(-h / Lm), c2 = (Real)(sqrt(-expm1(-2.0 * h / Lm)) / sqrt((double)d));
+      load_row<Real, 1>(U + m * ld, r, T, d, act, u);
+      double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        v[0] += (double)x[0][i] * (double)x[0][i];
+        v[1] += (double)g[0][i] * (double)g[0][i];
+        v[2] += (double)g[0][i] * (double)u[0][i];
+      }
+      team_sum<3>(v, T, red, slot);
+      const double l1 = lps - 0.5 * v[0];
+      const BMap b2 = b_map(v[1], v[2], h, dm1);
+      lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, 0, z);
+      double w1[1] = {0.0};
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const Real w = c1 * ((Real)b2.A * u[0][i] + (Real)b2.Bg * g[0][i]) + c2 * z[0][i];
+        u[0][i] = w;
+        w1[0] += (double)w * (double)w;
+      }
+      team_sum<1>(w1, T, red, slot);
+      const Real inw = (Real)(1.0 / sqrt(w1[0]));
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[0][i] *= inw;
+      if (act) {
+        store_row<Real, 1>(U + m * ld, r, T, d, u);
+        store_row<Real, 1>(Gc + m * ld, r, T, d, g);
+        if (r == 0) {
+          a.logp[m] = l1;
+          a.delta[m] = (sc_l0[m] - l1) + sc_dk[m] + b2.dK;
+        }
+        double K[1][8];
+        load_shift<1>(a.shiftK, r, T, d, K);
+        accumulate_stats<Real, 1>(S, K, x, g);
+      }
+    }
+    write_partials<Real, 1>(a.partials, d, ld, S, red, T, r);
+    return;
+  }
+
+  if (mode == LR_PRE) {
+    const double Lm = H->L;
+    const Real c1 = (Real)exp(-h / Lm), c2 = (Real)(sqrt(-expm1(-2.0 * h / Lm)) / sqrt((double)d));
+    load_row<Real, 1>(U + m * ld, r, T, d, act, u);
+    load_row<Real, 1>(Gc + m * ld, r, T, d, act, g);
+    lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_FIRST, 0, z);
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const Real w = c1 * u[0][i] + c2 * z[0][i];
+      u[0][i] = w;
+      v[0] += (double)w * (double)w;
+      v[1] += (double)g[0][i] * (double)w;
+      v[2] += (double)g[0][i] * (double)g[0][i];
+    }
+    team_sum<3>(v, T, red, slot);
+    const double inw = 1.0 / sqrt(v[0]);
+    const BMap b1 = b_map(v[2], v[1] * inw, h, dm1);
+    const Real A1 = (Real)(b1.A * inw), B1 = (Real)b1.Bg, epsR = (Real)eps;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      u[0][i] = A1 * u[0][i] + B1 * g[0][i];
+      x[0][i] += epsR * u[0][i];
+    }
+    if (act) {
+      store_row<Real, 1>(X + m * ld, r, T, d, x);
+      store_row<Real, 1>(U + m * ld, r, T, d, u);
+      if (r == 0) {
+        sc_l0[m] = a.logp[m];
+        sc_dk[m] = b1.dK;
+      }
+    }
+    return;
+  }
+
+  // adjusted phase: preconditioned MAMS trajectory, one stage per launch
+  const Coeffs C = integrator_coeffs(a.integ);
+  const double Lp = a.Lp_factor * (double)a.n_traj * eps;
+  const Real c1 = (Real)exp(-h / Lp), c2 = (Real)(sqrt(-expm1(-2.0 * h / Lp)) / sqrt((double)d));
+  Real sg[1][8];
+  load_row<Real, 1>(static_cast<const Real *>(a.sigma), r, T, d, true, sg);
+  double D = 0.0, lprev = 0.0;
+
+  // first half of a step: O_{eps/2}(j), B_{b0 eps}, A_{a0 eps}
+  auto step_start = [&](int j) {
+    lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_FIRST, (uint32_t)j, z);
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const Real w = c1 * u[0][i] + c2 * z[0][i];
+      const Real gt = sg[0][i] * g[0][i];
+      u[0][i] = w;
+      v[0] += (double)w * (double)w;
+      v[1] += (double)gt * (double)w;
+      v[2] += (double)gt * (double)gt;
+    }
+    team_sum<3>(v, T, red, slot);
+    const double inw = 1.0 / sqrt(v[0]);
+    const BMap b = b_map(v[2], v[1] * inw, C.b[0] * eps, dm1);
+    D += b.dK;
+    const Real Ab = (Real)(b.A * inw), Bb = (Real)b.Bg, ha = (Real)(C.a[0] * eps);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      u[0][i] = Ab * u[0][i] + Bb * sg[0][i] * g[0][i];
+      x[0][i] += ha * sg[0][i] * u[0][i];
+    }
+  };
+
+  if (mode == LR_MBEGIN) {
+    load_row<Real, 1>(Gc + m * ld, r, T, d, act, g);
+    if (act) {
+      store_row<Real, 1>(X0 + m * ld, r, T, d, x);
+      store_row<Real, 1>(G0 + m * ld, r, T, d, g);
+    }
+    const double l0 = act ? a.logp[m] : 0.0;
+    lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_FULL_REFRESH, 0, z);
+    double v1[1] = {0.0};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v1[0] += (double)z[0][i] * (double)z[0][i];
+    team_sum<1>(v1, T, red, slot);
+    const Real iz = (Real)(1.0 / sqrt(v1[0]));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[0][i] = z[0][i] * iz;
+    step_start(0);
+    if (act) {
+      store_row<Real, 1>(X + m * ld, r, T, d, x);
+      store_row<Real, 1>(U + m * ld, r, T, d, u);
+      if (r == 0) {
+        sc_l0[m] = l0;
+        sc_lprev[m] = l0;
+        sc_D[m] = D;
+      }
+    }
+    return;
+  }
+
+  // LR_MSTEP: consume gradient k of step j
+  load_row<Real, 1>(U + m * ld, r, T, d, act, u);
+  double lps;
+  lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
+  double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const Real gt = sg[0][i] * g[0][i];
+    v[0] += (double)x[0][i] * (double)x[0][i];
+    v[1] += (double)gt * (double)gt;
+    v[2] += (double)gt * (double)u[0][i];
+  }
+  team_sum<3>(v, T, red, slot);
+  const double lnew = lps - 0.5 * v[0];
+  D = (act ? sc_D[m] + (sc_lprev[m] - lnew) : 0.0);
+  lprev = lnew;
+  const int k = a.k, j = a.j;
+  {
+    const BMap b = b_map(v[1], v[2], C.b[k + 1] * eps, dm1);
+    D += b.dK;
+    const Real Ab = (Real)b.A, Bb = (Real)b.Bg;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[0][i] = Ab * u[0][i] + Bb * sg[0][i] * g[0][i];
+  }
+  if (k + 1 < C.K - 1) {
+    const Real ha = (Real)(C.a[k + 1] * eps);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[0][i] += ha * sg[0][i] * u[0][i];
+  } else {
+    lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, (uint32_t)j, z);
+    double w1[1] = {0.0};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const Real w = c1 * u[0][i] + c2 * z[0][i];
+      u[0][i] = w;
+      w1[0] += (double)w * (double)w;
+    }
+    team_sum<1>(w1, T, red, slot);
+    const Real inw = (Real)(1.0 / sqrt(w1[0]));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[0][i] *= inw;
+    if (j + 1 < a.n_traj) {
+      step_start(j + 1);
+    } else {
+      // Metropolis test on the whole trajectory's energy error
+      const double wacc = exp(-D);
+      const bool nanD = (D != D);
+      const double am = nanD ? 0.0 : (wacc < 1.0 ? wacc : 1.0);
+      const double U01 = mh_uniform(a.seed, (uint64_t)m, t);
+      const bool accept = !nanD && (U01 < wacc);
+      if (act) {
+        if (accept) {
+          store_row<Real, 1>(X + m * ld, r, T, d, x);
+          store_row<Real, 1>(Gc + m * ld, r, T, d, g);
+          if (r == 0) a.logp[m] = lnew;
+        } else {
+          Real x0[1][8], g0[1][8];
+          load_row<Real, 1>(X0 + m * ld, r, T, d, true, x0);
+          load_row<Real, 1>(G0 + m * ld, r, T, d, true, g0);
+          store_row<Real, 1>(X + m * ld, r, T, d, x0);
+          store_row<Real, 1>(Gc + m * ld, r, T, d, g0);
+          if (r == 0) a.logp[m] = sc_l0[m];
+        }
+        if (r == 0) {
+          a.acc[m] = am;
+          a.delta[m] = D;
+        }
+      }
+      return;
+    }
+  }
+  if (act) {
+    store_row<Real, 1>(X + m * ld, r, T, d, x);
+    store_row<Real, 1>(U + m * ld, r, T, d, u);
+    store_row<Real, 1>(Gc + m * ld, r, T, d, g);
+    if (r == 0) {
+      sc_D[m] = D;
+      sc_lprev[m] = lprev;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s) {
+  const int KC = a.KC, NB = a.NB;
+  const LrOffsets off = logreg_layout(1, a.n, a.d, a.N, a.ld, a.S);
+  const int64_t total = (int64_t)NB * 2 * KC * 64 * 2 + (int64_t)NB * 32;
+  hipLaunchKernelGGL(k_lr_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const unsigned short *>(a.X), a.y, a.n, a.d, KC, NB,
+                     reinterpret_cast<unsigned short *>(a.scratch + off.Xf),
+                     reinterpret_cast<unsigned short *>(a.scratch + off.Xb), reinterpret_cast<float *>(a.scratch + off.yf));
+  return hipGetLastError();
+}
+
+// The staged kernel's LDS exceeds 64 KiB for d > 96: raise its limit once
+// (gfx950 provides 160 KiB per workgroup).
+template <int KC>
+static hipError_t launch_staged(dim3 grid, size_t shm, const LogregArgs &a, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_lr_grad_bf16<KC>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_lr_grad_bf16<KC>, grid, dim3(512), shm, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
+  if (prec == 0) {
+    const dim3 grid((unsigned)((a.N + 15) / 16), (unsigned)a.S);
+    const size_t shm = (size_t)(16 * a.ld + 16 * 64) * sizeof(double);
+    hipLaunchKernelGGL(k_lr_grad_f64, grid, dim3(256), shm, s, a);
+    return hipGetLastError();
+  }
+  const dim3 grid((unsigned)((a.N + 63) / 64), (unsigned)a.S);
+  const size_t shm = (size_t)2 * (2 * 4 * a.KC * 64 + 16) * 16;
+  switch (a.KC) {
+    case 1: return launch_staged<1>(grid, shm, a, s);
+    case 2: return launch_staged<2>(grid, shm, a, s);
+    case 3: return launch_staged<3>(grid, shm, a, s);
+    case 4: return launch_staged<4>(grid, shm, a, s);
+    case 5: hipLaunchKernelGGL(k_lr_grad_bf16_direct<5>, grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_lr_grad_bf16_direct<6>, grid, dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL(k_lr_grad_bf16_direct<7>, grid, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_lr_grad_bf16_direct<8>, grid, dim3(256), 0, s, a); break;
+    case 9: hipLaunchKernelGGL(k_lr_grad_bf16_direct<9>, grid, dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL(k_lr_grad_bf16_direct<10>, grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, size_t shmem, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_lr_update<double>, dim3(grid), dim3(256), shmem, s, a);
+  else
+    hipLaunchKernelGGL(k_lr_update<float>, dim3(grid), dim3(256), shmem, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace laps

@@ -56,7 +56,8 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["laps_config_default", "laps_row_stride", "laps_workspace_size", "laps_init", "laps_step_unadjusted",
            "laps_step_adjusted", "laps_ensemble_stats", "laps_target_eval", "laps_philox_words",
-           "laps_philox_normals", "laps_buffer", "laps_destroy", "laps_status_string", "laps_last_error"]
+           "laps_philox_normals", "laps_time_gradient", "laps_buffer", "laps_destroy", "laps_status_string",
+           "laps_last_error"]
 
 _lib = None
 
@@ -83,6 +84,7 @@ def lib():
         "laps_target_eval": (I32, [P, I32, P, P, P, I64, P]),
         "laps_philox_words": (I32, [P, P, I64, U64, P]),
         "laps_philox_normals": (I32, [U64, I64, I64, U64, U32, U32, I32, P, P]),
+        "laps_time_gradient": (I32, [P, I32, P]),
         "laps_buffer": (P, [P, I32]),
         "laps_destroy": (I32, [P]),
         "laps_status_string": (ctypes.c_char_p, [I32]),
@@ -222,10 +224,27 @@ class Sampler:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.per_dim = torch.empty((4, d), dtype=torch.float64, device=device)
         self.ctx = ctypes.c_void_p()
-        st = lib().laps_init(ctypes.byref(c), ctypes.byref(self.target.s), ctypes.c_void_p(self.x.data_ptr()),
+        self._init()
+
+    def _init(self):
+        st = lib().laps_init(ctypes.byref(self.cfg), ctypes.byref(self.target.s), ctypes.c_void_p(self.x.data_ptr()),
                              ctypes.c_void_p(self.u0.data_ptr()) if self.u0 is not None else None,
                              ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, _stream_ptr(), ctypes.byref(self.ctx))
         _check(st)
+
+    def reinit(self, x0):
+        """Starts a fresh run from x0 (a device tensor [N, d]) in the same memory."""
+        if self.ctx:
+            lib().laps_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+        self.x[:, :self.d].copy_(x0)
+        self._init()
+
+    def time_gradient(self, n_reps: int = 20) -> float:
+        """Mean milliseconds of one ensemble gradient evaluation (HIP events on the sampler's stream)."""
+        ms = ctypes.c_float(0.0)
+        _check(lib().laps_time_gradient(self.ctx, n_reps, ctypes.byref(ms)), self.ctx)
+        return ms.value
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)

@@ -1,0 +1,141 @@
+"""GPU parity of the logistic-regression target (the matrix-core path).
+
+FP64 (plain vector-ALU gradient): positions within 1e-10 per chain of the
+oracle after unadjusted steps and MAMS transitions.
+
+bf16 mixed (v_mfma_f32_16x16x32_bf16, float accumulation, FP32 state, FP64
+energy and reductions): X is bf16-exact by construction and theta enters as a
+bf16 hi + lo pair, so on identical states every z_n is off by at most
+2^-17 sum_i |X_ni theta_i| plus float accumulation; the residual r enters the
+second product rounded to bf16 (2^-9 relative).  The tests check log p and
+the gradient against those bounds on identical states, and a replayed run
+against the oracle.  Sizes are ragged in every tiled dimension: N not a
+multiple of 64 chains, n not a multiple of 32 rows, d not a multiple of 8/32.
+"""
+import numpy as np
+import pytest
+
+from paper_2601_16696_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "gpu tests need a GPU"
+    from paper_2601_16696_amd import laps
+    laps.lib()
+    return laps
+
+
+def _w(N=100, n=300, d=37, seed=11):
+    return workloads.logreg(n_chains=N, n=n, d=d, seed_data=1000 + seed, seed_x0=2000 + seed)
+
+
+def _oracle(orc, w, **cfg):
+    e = orc.Ensemble(orc.Target.from_workload(w), w["n_chains"], w["seed"], **cfg)
+    e.init(w["x0"])
+    return e
+
+
+def _rel_rows(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+@pytest.mark.parametrize("shape", [(100, 300, 37), (64, 32, 100), (130, 5000, 100), (40, 77, 300)])
+def test_gradient_at_init_f64(gpu, orc, shape):
+    N, n, d = shape
+    w = _w(N, n, d)
+    s = gpu.Sampler(w, "f64")
+    s.stats()
+    g = s.buffer("g").cpu().numpy()
+    lp = s.buffer("logp").cpu().numpy()
+    ot = orc.Target.from_workload(w)
+    ref = [ot.logp_grad(x) for x in w["x0"]]
+    lref = np.array([r[0] for r in ref])
+    gref = np.array([r[1] for r in ref])
+    assert np.max(np.abs(lp - lref) / np.maximum(np.abs(lref), 1.0)) < 1e-12
+    assert np.max(_rel_rows(g, gref)) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(100, 300, 37), (64, 32, 100), (130, 5000, 100), (40, 77, 300)])
+def test_gradient_at_init_bf16_error_bounds(gpu, orc, shape):
+    N, n, d = shape
+    w = _w(N, n, d)
+    s = gpu.Sampler(w, "bf16")
+    s.stats()
+    th = np.asarray(w["x0"], dtype=np.float32).astype(np.float64)  # the FP32 state
+    g = s.buffer("g").cpu().numpy().astype(np.float64)
+    lp = s.buffer("logp").cpu().numpy()
+    X, y = w["X"], w["y"]
+    ot = orc.Target.from_workload(w)
+    for m in range(N):
+        l_ref, g_ref = ot.logp_grad(th[m])
+        z = X @ th[m]
+        zabs = np.abs(X) @ np.abs(th[m])
+        dz = 2.0**-17 * zabs + 2.0**-22 * zabs * 2  # hi/lo residual + float accumulation
+        sig = 1 / (1 + np.exp(-z))
+        bound_l = np.sum(np.abs(y - sig) * dz + 0.25 * dz**2) + 1e-6 * np.sum(np.abs(z) + 1.0)
+        assert abs(lp[m] - l_ref) <= bound_l, (m, lp[m] - l_ref, bound_l)
+        # residual rounding to bf16 (and its dependence on z) bounds the gradient error
+        dr = 2.0**-9 * np.abs(y - sig) + 0.25 * dz + 1e-7
+        bound_g = np.abs(X).T @ dr + 1e-5 * (np.abs(X).T @ np.abs(y - sig)) + 1e-6 * np.abs(th[m])
+        assert np.all(np.abs(g[m] - g_ref) <= bound_g), (m, np.max(np.abs(g[m] - g_ref) / bound_g))
+
+
+def test_unadjusted_and_adjusted_f64(gpu, orc):
+    w = _w(100, 300, 37)
+    cfg = dict(switch_policy=1, max_steps_unadj=15, max_steps_total=400)
+    o = _oracle(orc, w, **cfg)
+    s = gpu.Sampler(w, "f64", **cfg)
+    for k in range(15):
+        o.step_unadjusted(1)
+        s.step_unadjusted(1)
+        so, sg = o.stats(), s.stats()
+        for key in ("eps", "L", "dtilde"):
+            assert abs(sg[key] - so[key]) <= 1e-9 * abs(so[key]), (k, key, sg[key], so[key])
+    x = s.positions().cpu().numpy()
+    assert np.max(_rel_rows(x, o.array("x"))) < 1e-10
+    assert so["phase"] == sg["phase"] == 1
+    for k in range(3):
+        o.step_adjusted(1)
+        s.step_adjusted(1)
+        so, sg = o.stats(), s.stats()
+        assert abs(sg["acc_mean"] - so["acc_mean"]) < 1e-8, (k, sg["acc_mean"], so["acc_mean"])
+        assert abs(sg["eps"] - so["eps"]) <= 1e-9 * so["eps"]
+        assert sg["t"] == so["t"] and sg["grads_per_chain"] == so["grads_per_chain"]
+    x = s.positions().cpu().numpy()
+    assert np.max(_rel_rows(x, o.array("x"))) < 1e-10
+    np.testing.assert_allclose(s.buffer("acc").cpu().numpy(), o.array("acc"), rtol=0, atol=1e-8)
+
+
+def test_mixed_replayed_against_oracle(gpu, orc):
+    """bf16 gradients steer the velocity; with the oracle replaying the GPU's
+    eps and L, positions stay within 2e-3 relative per chain over 10 steps and
+    the energy errors agree to the log p error bound."""
+    w = _w(100, 300, 37)
+    cfg = dict(switch_policy=1, max_steps_unadj=1000)
+    o = _oracle(orc, w, **cfg)
+    s = gpu.Sampler(w, "bf16", **cfg)
+    for k in range(10):
+        sg = s.stats()
+        o.set_hyper(sg["eps"], sg["L"])
+        o.step_unadjusted(1)
+        s.step_unadjusted(1)
+    x = s.positions().cpu().numpy()
+    err = _rel_rows(x, o.array("x"))
+    assert np.max(err) < 2e-3, np.max(err)
+    dl = s.buffer("delta").cpu().numpy() - o.array("delta")
+    assert np.max(np.abs(dl)) < 5e-2, np.max(np.abs(dl))
+
+
+def test_mixed_adjusted_runs_and_accepts(gpu, orc):
+    w = _w(256, 500, 64, seed=3)
+    s = gpu.Sampler(w, "bf16", switch_policy=1, max_steps_unadj=200, max_steps_total=200 + 15 * 12)
+    s.step_unadjusted(200)
+    s.step_adjusted(12)
+    st = s.stats()
+    assert st["phase"] == 2 and st["n_nonfinite"] == 0
+    assert abs(st["acc_mean"] - 0.7) < 0.15
+    assert np.all(np.isfinite(s.positions().cpu().numpy()))
