@@ -33,12 +33,25 @@ if ROOT not in sys.path:
 METRIC = "chain-grad evals/s & time to bias b²<0.01, mixed/batched vs plain FP64 GPU"
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of k_lr_grad_bf16<4> on the logistic-regression workload, from FETCH_SIZE and
+# WRITE_SIZE counters scaled by what they read for a plain copy of known size (x2.0 and x1.0); kept
+# with the counter summary under profiles/ and reset to None whenever the kernel changes.
+LR_GRAD_TRAFFIC_BYTES = 29.32e6
 
 
 def _run_once(s, x0, n_unadj, n_adj):
     s.reinit(x0)
     s.step_unadjusted(n_unadj)
     s.step_adjusted(n_adj)
+
+
+WORKLOADS = {
+    # name: (generator, default precision, gradient evaluations per step of the dominant kernel)
+    "logreg": ("logreg", "bf16"),
+    "gauss": ("gaussian", "f64"),
+    "stochvol": ("stochvol", "f32"),
+    "phi4": ("phi4", "f32"),
+}
 
 
 def gpu_throughput(w, prec, steps, warmup, n_unadj=1000, n_adj=67):
@@ -62,8 +75,17 @@ def gpu_throughput(w, prec, steps, warmup, n_unadj=1000, n_adj=67):
     return dict(ms=ms, value=grads / (ms * 1e-3), stats=st, grad_ms=grad_ms, sampler=s)
 
 
+CPU_SAMPLE = {  # about 10 s of single-threaded oracle work on the same workload
+    "logreg": dict(n_chains=256, n_unadj=10, n_adj=1),
+    "gauss": dict(n_chains=1024, n_unadj=600, n_adj=4),
+    "stochvol": dict(n_chains=512, n_unadj=20, n_adj=1),
+    "phi4": dict(n_chains=512, n_unadj=20, n_adj=1),
+}
+
+
 def cpu_baseline(w, n_chains=256, n_unadj=10, n_adj=1):
     from oracle import oracle as orc
+    n_chains = min(n_chains, w["n_chains"])
     sub = dict(w)
     sub["x0"] = w["x0"][:n_chains]
     sub["n_chains"] = n_chains
@@ -85,7 +107,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="bf16", choices=["bf16", "f64"])
+    ap.add_argument("--workload", default="logreg", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default=None, choices=["bf16", "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     args = ap.parse_args()
@@ -96,12 +119,34 @@ def main():
     import torch
     from paper_2601_16696_amd import laps, workloads
     laps.lib()
-    w = workloads.logreg()
-    N, n, d = w["n_chains"], w["X"].shape[0], w["d"]
+    gen, default_prec = WORKLOADS[args.workload]
+    prec = args.prec or default_prec
+    w = getattr(workloads, gen)()
+    N, d = w["n_chains"], w["d"]
 
-    r = gpu_throughput(w, args.prec, args.steps, args.warmup)
-    flops = 4.0 * n * d * N
-    achieved = flops / (r["grad_ms"] * 1e-3) / 1e12
+    r = gpu_throughput(w, prec, args.steps, args.warmup)
+    if args.workload == "logreg":
+        n = w["X"].shape[0]
+        work = 4.0 * n * d * N  # flops of X theta and X^T r per ensemble gradient
+        peak = PEAK_BF16_TFLOPS if prec == "bf16" else 78.6
+        achieved = work / (r["grad_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma" if prec == "bf16" else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": LR_GRAD_TRAFFIC_BYTES if prec == "bf16" else None,
+                "traffic_unit": "bytes per launch",
+                "kernel": "k_lr_grad_bf16<4>" if prec == "bf16" else "k_lr_grad_f64", "kernel_ms": r["grad_ms"],
+                "algorithmic_flops_per_launch": work}
+        precision = ("bf16 matrix-core gradient, fp32 state, fp64 energy error and reductions"
+                     if prec == "bf16" else "fp64 throughout")
+        extra = {"n": n}
+    else:
+        rs = 8 if prec == "f64" else 4
+        work = 2.0 * rs * d * N  # the gradient kernel reads x and writes the gradient once per chain
+        achieved = work / (r["grad_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_eval (target gradient)",
+                "kernel_ms": r["grad_ms"], "algorithmic_bytes_per_launch": work}
+        precision = "fp64 throughout" if prec == "f64" else "fp32 state, fp64 energy error and reductions"
+        extra = {}
     line = {
         "metric": METRIC,
         "value": r["value"],
@@ -113,39 +158,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if args.prec == "bf16" else "f64",
+        "dtype": prec,
         "data": "synthetic",
-        "config": {
-            "workload": f"{w['name']}: full LAPS run, 1000 unadjusted + 67 MAMS transitions",
-            "chains": N, "n": n, "d": d,
-            "precision": ("bf16 matrix-core gradient, fp32 state, fp64 energy error and reductions"
-                          if args.prec == "bf16" else "fp64 throughout"),
-            "grads_per_chain": r["stats"]["grads_per_chain"],
-            "parallelism": "single GPU",
-        },
-        "roofline": {
-            "bound": "mfma" if args.prec == "bf16" else "alu",
-            "achieved": achieved,
-            "peak": PEAK_BF16_TFLOPS if args.prec == "bf16" else 78.6,
-            "unit": "TFLOP/s",
-            "frac": achieved / (PEAK_BF16_TFLOPS if args.prec == "bf16" else 78.6),
-            "traffic": None,
-            "kernel": "k_lr_grad_bf16<4>" if args.prec == "bf16" else "k_lr_grad_f64",
-            "kernel_ms": r["grad_ms"],
-            "algorithmic_flops_per_launch": flops,
-        },
+        "config": dict({
+            "workload": f"{w['name']}: full LAPS run, 1000 unadjusted steps + 67 MAMS transitions",
+            "chains": N, "d": d, "precision": precision,
+            "grads_per_chain": r["stats"]["grads_per_chain"], "parallelism": "single GPU"}, **extra),
+        "roofline": roof,
         "final_state": {"acc_mean": r["stats"]["acc_mean"], "eps": r["stats"]["eps"], "t": r["stats"]["t"],
                         "n_nonfinite": r["stats"]["n_nonfinite"]},
     }
     del r["sampler"]
     torch.cuda.empty_cache()
-    if not args.no_f64 and args.prec == "bf16":
+    if not args.no_f64 and prec != "f64":
         r64 = gpu_throughput(w, "f64", 1, 0)
         line["f64_gpu"] = {"value": r64["value"], "ms_per_step": r64["ms"], "gradient_ms": r64["grad_ms"],
                            "speedup_of_mixed": line["value"] / r64["value"]}
         del r64["sampler"]
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w)
+        line["cpu_baseline"] = cpu_baseline(w, **CPU_SAMPLE[args.workload])
     print(json.dumps(line))
 
 

@@ -21,8 +21,9 @@ struct laps_ctx {
   hipStream_t stream;
   bool dbl;
   int64_t ld, Tw;
-  // launch shape of the per-chain kernels
-  int T, Q, tpw, block, G, nb;
+  // launch shape of the per-chain kernels; G = partial rows of the statistics
+  int T, Q, tpw, block, G, nb, grid_full;
+  bool split;
   size_t shmem;
   int integ;
   bool adj_started;
@@ -64,7 +65,8 @@ extern "C" void laps_config_default(laps_config *c, int64_t n_chains, int64_t d)
 namespace {
 
 struct Shape {
-  int T, Q, tpw, block, G, nb;
+  int T, Q, tpw, block, G, nb, grid_full;
+  bool split;
   size_t shmem;
 };
 
@@ -90,9 +92,18 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, Shape &s) {
   s.block = s.T <= 64 ? 256 : s.T;
   s.tpw = s.block / s.T;
   const int64_t need = (N + s.tpw - 1) / s.tpw;
-  int64_t gmax = s.T >= 256 ? 256 : 512;
-  if (const char *e = getenv("LAPS_GRID")) gmax = atol(e) > 0 ? atol(e) : gmax;
-  s.G = (int)(need < gmax ? need : gmax);
+  s.grid_full = (int)need;
+  // Small chains (one wavefront or less): the step kernel accumulates the
+  // per-dim sums itself over a capped grid.  Large chains: every chain gets a
+  // workgroup and a separate column-sum pass over 64 chain blocks.
+  s.split = s.T > 64;
+  if (s.split) {
+    s.G = (int)(N < 64 ? N : 64);
+  } else {
+    int64_t gmax = 512;
+    if (const char *e = getenv("LAPS_GRID")) gmax = atol(e) > 0 ? atol(e) : gmax;
+    s.G = (int)(need < gmax ? need : gmax);
+  }
   const int64_t ld = laps_row_stride(d);
   const size_t rs = dbl ? 8 : 4;
   const bool stage = kind != LAPS_GAUSS_DIAG;
@@ -119,6 +130,8 @@ bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
     s.block = 256;
     s.tpw = 256 / T;
     s.G = (int)((cfg->n_chains + s.tpw - 1) / s.tpw);
+    s.grid_full = s.G;
+    s.split = false;
     s.shmem = 2 * kRedSlots * sizeof(double) + (size_t)4 * 8 * T * 8;
     s.nb = (int)((cfg->d + 31) / 32);
     return true;
@@ -335,9 +348,15 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
   if (is_local(c->tg.kind)) {
     LocalArgs a = local_args(c);
     a.u0 = u0;
-    return launch_local(c->tg.kind, c->dbl, c->Q, kk, a, c->G, c->block, c->shmem, c->stream) == hipSuccess
-               ? LAPS_OK
-               : fail(c, hipGetLastError(), "per-chain kernel");
+    const bool phase_stats = kk == KK_INIT || kk == KK_UNADJ;
+    a.stats = (phase_stats && !c->split) ? 1 : 0;
+    a.cache = (phase_stats && c->split) ? 1 : 0;
+    const int grid = (phase_stats && !c->split) ? c->G : c->grid_full;
+    hipError_t e = launch_local(c->tg.kind, c->dbl, c->Q, kk, a, grid, c->block, c->shmem, c->stream);
+    if (e == hipSuccess && phase_stats && c->split)
+      e = launch_stats(c->dbl, c->x, c->g, c->shiftK, c->partials, c->cfg.n_chains, c->cfg.d, c->ld, c->G,
+                       kk == KK_UNADJ ? c->hyp : nullptr, c->stream);
+    return e == hipSuccess ? LAPS_OK : fail(c, e, "per-chain kernel");
   }
   const int prec = c->cfg.prec;
   auto upd = [&](LogregArgs &a, int mode, int j, int k) -> hipError_t {
@@ -425,6 +444,8 @@ extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, 
   c->tpw = s.tpw;
   c->block = s.block;
   c->G = s.G;
+  c->grid_full = s.grid_full;
+  c->split = s.split;
   c->nb = s.nb;
   c->shmem = s.shmem;
   c->integ = integ_for(cfg);
@@ -641,7 +662,7 @@ extern "C" laps_status laps_time_gradient(laps_ctx *c, int32_t n_reps, float *av
       LocalArgs a = local_args(c);
       a.logp_out = c->logp;
       a.g_out = c->g;
-      e = launch_local(c->tg.kind, c->dbl, c->Q, KK_EVAL, a, c->G, c->block, c->shmem, c->stream);
+      e = launch_local(c->tg.kind, c->dbl, c->Q, KK_EVAL, a, c->grid_full, c->block, c->shmem, c->stream);
     } else {
       LogregArgs a = logreg_args(c, 0);
       e = launch_logreg_grad(c->cfg.prec, a, c->stream);

@@ -212,13 +212,17 @@ __global__ void __launch_bounds__(1024) k_ctl_unadj(CtlArgs c) {
   const double mu = mean_sh;
   double sq, bad2;
   chain_sums(c.delta, c.N, c.eevpd_mode == 1 ? 0.0 : mu, 1, sq, bad2, sh);
-  if (threadIdx.x != 0) return;
-  double sD = 0.0, sV = 0.0, mx = -INFINITY;
-  for (int b = 0; b < c.nb; ++b) {
-    sD += c.part2[b * 4 + 0];
-    sV += c.part2[b * 4 + 1];
-    mx = nanmax(mx, c.part2[b * 4 + 2]);
+  // block scalars of the statistics pass, reduced in a fixed tree order
+  double p3[3] = {0.0, 0.0, -INFINITY};
+  for (int b = threadIdx.x; b < c.nb; b += blockDim.x) {
+    p3[0] += c.part2[b * 4 + 0];
+    p3[1] += c.part2[b * 4 + 1];
+    p3[2] = nanmax(p3[2], c.part2[b * 4 + 2]);
   }
+  const int op3[3] = {0, 0, 1};
+  block_reduce<3>(p3, op3, sh);
+  if (threadIdx.x != 0) return;
+  const double sD = p3[0], sV = p3[1], mx = p3[2];
   H->dtilde = sD / (double)c.d;
   H->eevpd = sq / (double)c.N / (double)c.d;
   H->n_nonfinite = (int64_t)bad;

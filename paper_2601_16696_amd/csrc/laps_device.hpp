@@ -179,6 +179,47 @@ __device__ __forceinline__ BMap b_map(double gg, double gu, double h, double dm1
   return r;
 }
 
+// The same map with the per-chain scalars in float, for the FP32 state: the
+// coefficients only multiply float vectors, and the energy term is returned
+// as a double for the FP64 energy accumulation.
+__device__ __forceinline__ BMap b_map_f(double gg, double gu, double h, double dm1) {
+  BMap r;
+  if (gg == 0.0) {
+    r.A = 1.0;
+    r.Bg = 0.0;
+    r.dK = 0.0;
+    return r;
+  }
+  const float n = sqrtf((float)gg);
+  const float delta = (float)h * n / (float)dm1;
+  const float c = (float)gu / n;
+  if (fabsf(delta) < 20.0f) {
+    const float sh = sinhf(delta);
+    const float shh = sinhf(0.5f * delta);
+    const float chm1 = 2.0f * shh * shh;
+    const float Dm1 = chm1 + c * sh;
+    const float invD = 1.0f / (1.0f + Dm1);
+    r.A = invD;
+    r.Bg = (sh + c * chm1) / n * invD;
+    r.dK = dm1 * (double)log1pf(Dm1);
+  } else {
+    const float ad = fabsf(delta);
+    const float e2 = expf(-2.0f * ad);
+    const float tau = copysignf((1.0f - e2) / (1.0f + e2), delta);
+    const float sech = 2.0f * expf(-ad) / (1.0f + e2);
+    const float Dh = 1.0f + c * tau;
+    r.A = sech / Dh;
+    r.Bg = (tau + c * (1.0f - sech)) / n / Dh;
+    r.dK = dm1 * ((double)ad + (double)log1pf(e2) - 0.69314718055994531 + (double)logf(Dh));
+  }
+  return r;
+}
+
+template <class Real>
+__device__ __forceinline__ BMap b_map_t(double gg, double gu, double h, double dm1) {
+  return sizeof(Real) == 8 ? b_map(gg, gu, h, dm1) : b_map_f(gg, gu, h, dm1);
+}
+
 // Integrator coefficient sets (Table "Integrators"): symmetric B A B ... B,
 // the coefficients not printed follow from symmetry and normalisation.
 struct Coeffs {

@@ -31,6 +31,7 @@ struct LocalArgs {
   int n_traj;
   double Lp_factor;
   int cache;               // store g and log p (1) or recompute them (0)
+  int stats;               // accumulate per-dim sums in the step kernel (1) or leave them to k_stats (0)
   double *logp_out;        // target eval: log p output
   void *g_out;             // target eval: gradient output (or null)
 };
@@ -70,6 +71,11 @@ enum KernelKind { KK_INIT = 0, KK_UNADJ = 1, KK_MAMS_MN2 = 2, KK_MAMS_MN4 = 3, K
 hipError_t launch_local(int kind, bool dbl, int Q, KernelKind kk, const LocalArgs &a, int grid, int block,
                         size_t shmem, hipStream_t s);
 hipError_t launch_prep_aux(int kind, bool dbl, const void *src, void *aux, int64_t d, int64_t ld, hipStream_t s);
+// Per-dimension ensemble sums of (x - K, (x - K)^2, (x - K) g, g) over CB
+// chain blocks, one partial row per block (used when the step kernel does not
+// accumulate them itself).
+hipError_t launch_stats(bool dbl, const void *x, const void *g, const double *shiftK, double *partials, int64_t N,
+                        int64_t d, int64_t ld, int CB, const DevHyper *hyp, hipStream_t s);
 
 // Logistic regression.  The gradient kernels split the n data rows over S
 // workgroup columns and write per-split partial sums (G = X^T r rows and

@@ -184,6 +184,18 @@ struct SVTgt {
   }
 };
 
+// Integrator coefficients by integrator id (0 LF, 1 MN2, 2 MN4), in constant
+// memory so that a rolled loop over the composition reads them by index.
+__constant__ double kCoefB[3][6] = {
+    {0.5, 0.5, 0.0, 0.0, 0.0, 0.0},
+    {0.1931833275, 1.0 - 2.0 * 0.1931833275, 0.1931833275, 0.0, 0.0, 0.0},
+    {0.0839831526, 0.6822365335, 0.5 - 0.0839831526 - 0.6822365335, 0.5 - 0.0839831526 - 0.6822365335, 0.6822365335,
+     0.0839831526}};
+__constant__ double kCoefA[3][5] = {
+    {1.0, 0.0, 0.0, 0.0, 0.0},
+    {0.5, 0.5, 0.0, 0.0, 0.0},
+    {0.2539785108, -0.032302867, 1.0 - 2.0 * (0.2539785108 - 0.032302867), -0.032302867, 0.2539785108}};
+
 // ---------------------------------------------------------------------------
 // shared kernel prologue
 // ---------------------------------------------------------------------------
@@ -202,7 +214,7 @@ struct SVTgt {
 // random direction when the gradient vanishes), per-dim sums for the initial
 // variances (shift K = 0).
 // ---------------------------------------------------------------------------
-template <class Real, int Q, class Tgt>
+template <class Real, int Q, class Tgt, bool STATS>
 __global__ void __launch_bounds__(512) k_init(LocalArgs a) {
   LAPS_TEAM_PROLOGUE
   Tgt tgt;
@@ -246,10 +258,10 @@ __global__ void __launch_bounds__(512) k_init(LocalArgs a) {
         a.delta[m] = 0.0;
         a.acc[m] = 0.0;
       }
-      accumulate_stats<Real, Q>(S, K0, x, g);
+      if (STATS) accumulate_stats<Real, Q>(S, K0, x, g);
     }
   }
-  write_partials<Real, Q>(a.partials, a.d, a.ld, S, red, T, r);
+  if (STATS) write_partials<Real, Q>(a.partials, a.d, a.ld, S, red, T, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -260,8 +272,8 @@ __global__ void __launch_bounds__(512) k_init(LocalArgs a) {
 // reduction (g.u = g.w / |w|).  Ensemble sums of the new state go to the
 // workgroup's partial row.
 // ---------------------------------------------------------------------------
-template <class Real, int Q, class Tgt>
-__global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
+template <class Real, int Q, class Tgt, bool STATS>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(STATS ? 1 : 3))) k_unadj(LocalArgs a) {
   const DevHyper *H = a.hyp;
   if (H->phase != PH_UNADJ) return;
   LAPS_TEAM_PROLOGUE
@@ -274,7 +286,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
   tgt.setup(a, r, T);
   double S[4][Q][8] = {};
   double K[Q][8];
-  load_shift<Q>(a.shiftK, r, T, d, K);
+  if (STATS) load_shift<Q>(a.shiftK, r, T, d, K);
   Real *X = static_cast<Real *>(a.x);
   Real *U = static_cast<Real *>(a.u);
   for (int64_t base = (int64_t)blockIdx.x * a.tpw; base < N; base += (int64_t)gridDim.x * a.tpw) {
@@ -299,7 +311,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
       }
     team_sum<4>(v4, T, red, slot);
     const double inw = 1.0 / sqrt(v4[1]);
-    const BMap b1 = b_map(v4[3], v4[2] * inw, h, dm1);
+    const BMap b1 = b_map_t<Real>(v4[3], v4[2] * inw, h, dm1);
     const Real A1 = (Real)(b1.A * inw), B1 = (Real)b1.Bg;
 #pragma unroll
     for (int q = 0; q < Q; ++q)
@@ -318,7 +330,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
         v3[2] += (double)g[q][i] * (double)u[q][i];
       }
     team_sum<3>(v3, T, red, slot);
-    const BMap b2 = b_map(v3[1], v3[2], h, dm1);
+    const BMap b2 = b_map_t<Real>(v3[1], v3[2], h, dm1);
     const Real A2 = (Real)b2.A, B2 = (Real)b2.Bg;
     lane_normals<Real, Q>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, 0, z);
     double v1[1] = {0.0};
@@ -344,10 +356,10 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
         a.delta[m] = (v4[0] - v3[0]) + b1.dK + b2.dK;
         a.logp[m] = v3[0];
       }
-      accumulate_stats<Real, Q>(S, K, x, g);
+      if (STATS) accumulate_stats<Real, Q>(S, K, x, g);
     }
   }
-  write_partials<Real, Q>(a.partials, a.d, a.ld, S, red, T, r);
+  if (STATS) write_partials<Real, Q>(a.partials, a.d, a.ld, S, red, T, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,7 +372,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
 // keep their starting values.
 // ---------------------------------------------------------------------------
 template <class Real, int Q, class Tgt, int INTEG>
-__global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k_mams(LocalArgs a) {
   const DevHyper *H = a.hyp;
   if (H->phase != PH_ADJ || H->t >= a.max_total) return;
   LAPS_TEAM_PROLOGUE
@@ -414,7 +426,7 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
         }
       team_sum<3>(v3, T, red, slot);
       const double inw = 1.0 / sqrt(v3[0]);
-      BMap b = b_map(v3[2], v3[1] * inw, C.b[0] * eps, dm1);
+      BMap b = b_map_t<Real>(v3[2], v3[1] * inw, C.b[0] * eps, dm1);
       D += b.dK;
       {
         const Real Ab = (Real)(b.A * inw), Bb = (Real)b.Bg;
@@ -424,9 +436,9 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
           for (int i = 0; i < 8; ++i) u[q][i] = Ab * u[q][i] + Bb * sg[q][i] * g[q][i];
       }
       constexpr int KB = INTEG == 2 ? 6 : (INTEG == 1 ? 3 : 2);
-#pragma unroll
+#pragma unroll 1
       for (int k = 0; k < KB - 1; ++k) {
-        const Real ha = (Real)(C.a[k] * eps);
+        const Real ha = (Real)(kCoefA[INTEG][k] * eps);
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -444,7 +456,7 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
         team_sum<3>(w3, T, red, slot);
         D += lp - w3[0];
         lp = w3[0];
-        b = b_map(w3[1], w3[2], C.b[k + 1] * eps, dm1);
+        b = b_map_t<Real>(w3[1], w3[2], kCoefB[INTEG][k + 1] * eps, dm1);
         D += b.dK;
         const Real Ab = (Real)b.A, Bb = (Real)b.Bg;
 #pragma unroll
@@ -509,6 +521,60 @@ __global__ void __launch_bounds__(512) k_eval(LocalArgs a) {
   }
 }
 
+// Column sums over a block of chains: thread i of grid column cb owns
+// dimension i and walks chains cb, cb + CB, ... in order (coalesced across the
+// threads of a row).
+template <class Real>
+__global__ void __launch_bounds__(256) k_stats(const Real *x, const Real *g, const double *shiftK, double *partials,
+                                               int64_t N, int64_t d, int64_t ld, int CB, const DevHyper *hyp) {
+  if (hyp && hyp->phase != PH_UNADJ) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int cb = blockIdx.y;
+  if (i >= d) return;
+  const double K = shiftK[i];
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+  int64_t m = cb;
+  for (; m + 3 * CB < N; m += 4 * CB) {
+    double xv[4], gv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xv[k] = (double)x[(m + k * CB) * ld + i] - K;
+      gv[k] = (double)g[(m + k * CB) * ld + i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s1 += xv[k];
+      s2 += xv[k] * xv[k];
+      s3 += xv[k] * gv[k];
+      s4 += gv[k];
+    }
+  }
+  for (; m < N; m += CB) {
+    const double xv = (double)x[m * ld + i] - K, gv = (double)g[m * ld + i];
+    s1 += xv;
+    s2 += xv * xv;
+    s3 += xv * gv;
+    s4 += gv;
+  }
+  double *P = partials + (size_t)cb * 4 * ld;
+  P[i] = s1;
+  P[ld + i] = s2;
+  P[2 * ld + i] = s3;
+  P[3 * ld + i] = s4;
+}
+
+hipError_t launch_stats(bool dbl, const void *x, const void *g, const double *shiftK, double *partials, int64_t N,
+                        int64_t d, int64_t ld, int CB, const DevHyper *hyp, hipStream_t s) {
+  const dim3 grid((unsigned)((d + 255) / 256), (unsigned)CB);
+  if (dbl)
+    hipLaunchKernelGGL(k_stats<double>, grid, dim3(256), 0, s, (const double *)x, (const double *)g, shiftK,
+                       partials, N, d, ld, CB, hyp);
+  else
+    hipLaunchKernelGGL(k_stats<float>, grid, dim3(256), 0, s, (const float *)x, (const float *)g, shiftK, partials,
+                       N, d, ld, CB, hyp);
+  return hipGetLastError();
+}
+
 // per-dim constants of the targets in the state type: 1/s2 (Gaussian), y^2 (SV)
 template <class Real>
 __global__ void k_prep_aux(int kind, const double *src, Real *aux, int64_t d, int64_t ld) {
@@ -526,8 +592,18 @@ __global__ void k_prep_aux(int kind, const double *src, Real *aux, int64_t d, in
 template <class Real, int Q, class Tgt>
 static hipError_t launch_kind(KernelKind kk, const LocalArgs &a, int grid, int block, size_t shmem, hipStream_t s) {
   switch (kk) {
-    case KK_INIT: hipLaunchKernelGGL((k_init<Real, Q, Tgt>), dim3(grid), dim3(block), shmem, s, a); break;
-    case KK_UNADJ: hipLaunchKernelGGL((k_unadj<Real, Q, Tgt>), dim3(grid), dim3(block), shmem, s, a); break;
+    case KK_INIT:
+      if (a.stats)
+        hipLaunchKernelGGL((k_init<Real, Q, Tgt, true>), dim3(grid), dim3(block), shmem, s, a);
+      else
+        hipLaunchKernelGGL((k_init<Real, Q, Tgt, false>), dim3(grid), dim3(block), shmem, s, a);
+      break;
+    case KK_UNADJ:
+      if (a.stats)
+        hipLaunchKernelGGL((k_unadj<Real, Q, Tgt, true>), dim3(grid), dim3(block), shmem, s, a);
+      else
+        hipLaunchKernelGGL((k_unadj<Real, Q, Tgt, false>), dim3(grid), dim3(block), shmem, s, a);
+      break;
     case KK_MAMS_MN2: hipLaunchKernelGGL((k_mams<Real, Q, Tgt, 1>), dim3(grid), dim3(block), shmem, s, a); break;
     case KK_MAMS_MN4: hipLaunchKernelGGL((k_mams<Real, Q, Tgt, 2>), dim3(grid), dim3(block), shmem, s, a); break;
     case KK_EVAL: hipLaunchKernelGGL((k_eval<Real, Q, Tgt>), dim3(grid), dim3(block), shmem, s, a); break;

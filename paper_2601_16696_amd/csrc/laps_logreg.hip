@@ -18,6 +18,8 @@
 //
 // Plain FP64 (LAPS_F64): the same partial-sum interface with a double-precision
 // vector-ALU gradient (the baseline the mixed path is measured against).
+#include <stdlib.h>
+
 #include "laps_team.hpp"
 
 namespace laps {
@@ -29,7 +31,9 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 void logreg_splits(int64_t n, int64_t N, int &S, int &NB, int &bps) {
   NB = (int)((n + 31) / 32);
   const int64_t groups = (N + 63) / 64;
-  int64_t want = 256 / (groups > 0 ? groups : 1);
+  int64_t target = 256;  // workgroups of one gradient launch (one per CU)
+  if (const char *e = getenv("LAPS_LR_WGS")) target = atol(e) > 0 ? atol(e) : target;
+  int64_t want = target / (groups > 0 ? groups : 1);
   if (want < 1) want = 1;
   if (want > NB) want = NB;
   bps = (int)((NB + want - 1) / want);
@@ -542,7 +546,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
       }
       team_sum<3>(v, T, red, slot);
       const double l1 = lps - 0.5 * v[0];
-      const BMap b2 = b_map(v[1], v[2], h, dm1);
+      const BMap b2 = b_map_t<Real>(v[1], v[2], h, dm1);
       lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, 0, z);
       double w1[1] = {0.0};
 #pragma unroll
@@ -588,7 +592,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     }
     team_sum<3>(v, T, red, slot);
     const double inw = 1.0 / sqrt(v[0]);
-    const BMap b1 = b_map(v[2], v[1] * inw, h, dm1);
+    const BMap b1 = b_map_t<Real>(v[2], v[1] * inw, h, dm1);
     const Real A1 = (Real)(b1.A * inw), B1 = (Real)b1.Bg, epsR = (Real)eps;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -629,7 +633,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     }
     team_sum<3>(v, T, red, slot);
     const double inw = 1.0 / sqrt(v[0]);
-    const BMap b = b_map(v[2], v[1] * inw, C.b[0] * eps, dm1);
+    const BMap b = b_map_t<Real>(v[2], v[1] * inw, C.b[0] * eps, dm1);
     D += b.dK;
     const Real Ab = (Real)(b.A * inw), Bb = (Real)b.Bg, ha = (Real)(C.a[0] * eps);
 #pragma unroll
@@ -685,7 +689,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   lprev = lnew;
   const int k = a.k, j = a.j;
   {
-    const BMap b = b_map(v[1], v[2], C.b[k + 1] * eps, dm1);
+    const BMap b = b_map_t<Real>(v[1], v[2], C.b[k + 1] * eps, dm1);
     D += b.dK;
     const Real Ab = (Real)b.A, Bb = (Real)b.Bg;
 #pragma unroll
