@@ -113,6 +113,10 @@ typedef struct {
   double C, alpha, eps0_factor, switch_tol, window_frac, acc_tol, acc_target, L_partial_factor;
   int32_t n_steps_traj, integrator_adj, eevpd_mode, switch_policy;
   int64_t max_steps_unadj, max_steps_total;
+  int32_t team_lanes; /* launch shape of the per-chain kernels (Gaussian, SV, phi4):
+                         0 = automatic; otherwise lanes per chain, a power of two
+                         up to 64 or a multiple of 64 up to 512 */
+  int32_t reserved0;  /* zero */
 } laps_config;
 
 /* Snapshot of the device-resident hyperparameters and diagnostics.

@@ -24,7 +24,7 @@ struct laps_ctx {
   // launch shape of the per-chain kernels; G = partial rows of the statistics
   int T, Q, tpw, block, G, nb, grid_full;
   bool split;
-  size_t shmem;
+  size_t shmem, shmem_sig;
   int integ;
   bool adj_started;
   // workspace
@@ -67,36 +67,63 @@ namespace {
 struct Shape {
   int T, Q, tpw, block, G, nb, grid_full;
   bool split;
-  size_t shmem;
+  size_t shmem, shmem_sig;  // dynamic LDS without / with the preconditioner row
 };
 
 bool is_local(int kind) { return kind == LAPS_GAUSS_DIAG || kind == LAPS_STOCHVOL || kind == LAPS_PHI4; }
 
-// Team shape: the chain's ceil(d/8) octs over T lanes, Q octs per lane.
-bool local_shape(int kind, bool dbl, int64_t N, int64_t d, Shape &s) {
+// Team shape of the per-chain kernels: the chain's ceil(d/8) octs over T
+// lanes, Q octs per lane.  Short chains get one oct per lane (T the next power
+// of two) and accumulate the per-dim sums in registers; longer chains take a
+// whole wavefront (T = 64) with Q octs per lane, so that the per-chain scalar
+// work is shared by 8 Q coordinates per lane; only chains longer than 64 lanes
+// x Q_max octs use multi-wavefront teams.  FP64 state keeps up to 2 octs per
+// lane in registers, FP32 up to 6.
+bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape &s) {
   const int64_t octs = (d + 7) / 8;
-  if (octs <= 64) {
-    int T = 1;
+  // a phi^4 lattice whose rows are not whole octs runs one oct per lane
+  const int64_t side = kind == LAPS_PHI4 ? (int64_t)llround(sqrt((double)d)) : 0;
+  const int64_t qmax = (kind == LAPS_PHI4 && side % 8 != 0) ? 1 : (dbl ? 2 : 6);
+  int64_t T;
+  if (team_lanes > 0) {
+    T = team_lanes;
+    const bool pow2 = (T & (T - 1)) == 0;
+    if (!((T <= 64 && pow2) || (T % 64 == 0 && T <= 512))) return false;
+  } else if (octs <= 64) {
+    T = 1;
     while (T < octs) T <<= 1;
-    s.T = T;
-    s.Q = 1;
-  } else if (octs <= 512) {
-    s.Q = 1;
-    s.T = (int)round_up(octs, 64);
-  } else if (octs <= 1024) {
-    s.Q = 2;
-    s.T = (int)round_up((octs + 1) / 2, 64);
+  } else if (octs <= 64 * qmax) {
+    T = 64;
   } else {
-    return false;
+    T = 64 * ((octs + 64 * qmax - 1) / (64 * qmax));
+    if (T > 512) return false;
   }
-  s.block = s.T <= 64 ? 256 : s.T;
-  s.tpw = s.block / s.T;
+  const int64_t Q = (octs + T - 1) / T;
+  if (Q > qmax) return false;
+  s.T = (int)T;
+  s.Q = (int)Q;
+  s.split = !(Q == 1 && T <= 64);
+  const int64_t ld = laps_row_stride(d);
+  const size_t rs = dbl ? 8 : 4;
+  const bool aux = kind != LAPS_PHI4;
+  const bool stage = kind == LAPS_PHI4 || (kind == LAPS_STOCHVOL && T > 64);
+  const size_t fixed = 2 * kRedSlots * sizeof(double) + (aux ? (size_t)ld * rs : 0);
+  auto body = [&](int64_t blk) -> size_t {
+    size_t b = stage ? (size_t)(blk / T) * ld * rs : 0;
+    if (!s.split && blk > T) {
+      const size_t pb = (size_t)4 * 8 * Q * T * 8;  // staging of the per-dim partial row
+      if (pb > b) b = pb;
+    }
+    return b;
+  };
+  // Up to 256 threads per workgroup; fewer when the teams' chain copies would
+  // take more than 56 KiB of LDS (which would cap the resident wavefronts).
+  int64_t block = T <= 64 ? 256 : T;
+  while (T <= 64 && block > T && block > 64 && fixed + body(block) + (size_t)ld * rs > 56 * 1024) block >>= 1;
+  s.block = (int)block;
+  s.tpw = (int)(block / T);
   const int64_t need = (N + s.tpw - 1) / s.tpw;
   s.grid_full = (int)need;
-  // Small chains (one wavefront or less): the step kernel accumulates the
-  // per-dim sums itself over a capped grid.  Large chains: every chain gets a
-  // workgroup and a separate column-sum pass over 64 chain blocks.
-  s.split = s.T > 64;
   if (s.split) {
     s.G = (int)(N < 64 ? N : 64);
   } else {
@@ -104,22 +131,15 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, Shape &s) {
     if (const char *e = getenv("LAPS_GRID")) gmax = atol(e) > 0 ? atol(e) : gmax;
     s.G = (int)(need < gmax ? need : gmax);
   }
-  const int64_t ld = laps_row_stride(d);
-  const size_t rs = dbl ? 8 : 4;
-  const bool stage = kind != LAPS_GAUSS_DIAG;
-  size_t body = stage ? (size_t)s.tpw * ld * rs : 0;
-  if (s.tpw > 1) {
-    const size_t pb = (size_t)4 * 8 * s.Q * s.T * 8;
-    if (pb > body) body = pb;
-  }
-  s.shmem = 2 * kRedSlots * sizeof(double) + body;
+  s.shmem = fixed + body(block);
+  s.shmem_sig = s.shmem + (size_t)ld * rs;
   s.nb = (int)((d + 31) / 32);
   return true;
 }
 
 bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
   const bool dbl = cfg->prec == LAPS_F64;
-  if (is_local(tg->kind)) return local_shape(tg->kind, dbl, cfg->n_chains, cfg->d, s);
+  if (is_local(tg->kind)) return local_shape(tg->kind, dbl, cfg->n_chains, cfg->d, cfg->team_lanes, s);
   if (tg->kind == LAPS_LOGREG) {
     const int64_t octs = (cfg->d + 7) / 8;
     if (cfg->d > 320) return false;
@@ -133,6 +153,7 @@ bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
     s.grid_full = s.G;
     s.split = false;
     s.shmem = 2 * kRedSlots * sizeof(double) + (size_t)4 * 8 * T * 8;
+    s.shmem_sig = s.shmem;
     s.nb = (int)((cfg->d + 31) / 32);
     return true;
   }
@@ -200,6 +221,7 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
   if (!(cfg->window_frac > 0.0) || !(cfg->C > 0.0) || !(cfg->alpha > 0.0) || !(cfg->eps0_factor > 0.0) ||
       !(cfg->L_partial_factor > 0.0))
     return why = "non-positive constant in config", LAPS_EINVAL;
+  if (cfg->team_lanes < 0) return why = "team_lanes must be >= 0", LAPS_EINVAL;
   if (cfg->integrator_adj < 0 || cfg->integrator_adj > 2 || cfg->eevpd_mode < 0 || cfg->eevpd_mode > 1 ||
       cfg->switch_policy < 0 || cfg->switch_policy > 1)
     return why = "bad enum in config", LAPS_EINVAL;
@@ -352,7 +374,9 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     a.stats = (phase_stats && !c->split) ? 1 : 0;
     a.cache = (phase_stats && c->split) ? 1 : 0;
     const int grid = (phase_stats && !c->split) ? c->G : c->grid_full;
-    hipError_t e = launch_local(c->tg.kind, c->dbl, c->Q, kk, a, grid, c->block, c->shmem, c->stream);
+    const bool mams = kk == KK_MAMS_MN2 || kk == KK_MAMS_MN4;
+    hipError_t e = launch_local(c->tg.kind, c->dbl, c->Q, kk, a, grid, c->block, mams ? c->shmem_sig : c->shmem,
+                                c->stream);
     if (e == hipSuccess && phase_stats && c->split)
       e = launch_stats(c->dbl, c->x, c->g, c->shiftK, c->partials, c->cfg.n_chains, c->cfg.d, c->ld, c->G,
                        kk == KK_UNADJ ? c->hyp : nullptr, c->stream);
@@ -448,6 +472,7 @@ extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, 
   c->split = s.split;
   c->nb = s.nb;
   c->shmem = s.shmem;
+  c->shmem_sig = s.shmem_sig;
   c->integ = integ_for(cfg);
   c->adj_started = false;
   char *w = static_cast<char *>(ws_dev);
@@ -469,7 +494,7 @@ extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, 
   c->sigma = w + L.sigma;
   c->aux = w + L.aux;
   c->packed = w + L.packed;
-  if (c->shmem > 64 * 1024) {
+  if (c->shmem_sig > 64 * 1024) {
     // larger dynamic LDS needs the attribute on every instantiation; this build keeps within 64 KiB
     delete c;
     g_last_global = "team shape needs more than 64 KiB of LDS";
@@ -586,8 +611,7 @@ extern "C" laps_status laps_target_eval(const laps_target *tg, int32_t prec, con
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (is_local(tg->kind)) {
     Shape sh;
-    local_shape(tg->kind, prec == LAPS_F64, n, tg->d, sh);
-    if (sh.shmem > 64 * 1024) return LAPS_EUNSUPPORTED;
+    if (!local_shape(tg->kind, prec == LAPS_F64, n, tg->d, 0, sh) || sh.shmem > 64 * 1024) return LAPS_EUNSUPPORTED;
     LocalArgs a{};
     a.x = const_cast<void *>(x_dev);
     a.aux = nullptr;

@@ -65,6 +65,11 @@ __device__ __forceinline__ void normals8<double>(uint64_t seed, uint64_t m, uint
   }
 }
 
+// FP32 state: the same uniforms, with the hardware base-2 logarithm, square
+// root and the sine/cosine of an angle given in revolutions (U_b is already a
+// fraction of a turn, so no range reduction is needed).  Each of these has a
+// relative (log2, sqrt) or absolute (sin, cos) error near 1e-7 on (0, 1], so
+// the normals carry an absolute error of order 1e-6 against FP64.
 template <>
 __device__ __forceinline__ void normals8<float>(uint64_t seed, uint64_t m, uint64_t oct, uint64_t t, uint32_t tag,
                                                 uint32_t substep, float (&z)[8]) {
@@ -74,11 +79,10 @@ __device__ __forceinline__ void normals8<float>(uint64_t seed, uint64_t m, uint6
   for (int k = 0; k < 4; ++k) {
     const float ua = fmaf((float)(uint32_t)(c[k] >> 32), 2.3283064365386963e-10f, 1.1641532182693481e-10f);
     const float ub = fmaf((float)(uint32_t)c[k], 2.3283064365386963e-10f, 1.1641532182693481e-10f);
-    const float r = sqrtf(-2.0f * logf(ua));
-    float s, co;
-    sincospif(2.0f * ub, &s, &co);
-    z[2 * k] = r * co;
-    z[2 * k + 1] = r * s;
+    // -2 ln U = -2 ln(2) log2(U)
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+    z[2 * k] = r * __builtin_amdgcn_cosf(ub);
+    z[2 * k + 1] = r * __builtin_amdgcn_sinf(ub);
   }
 }
 
@@ -139,8 +143,9 @@ __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || 
 //   u' = (u + (sinh delta + c (cosh delta - 1)) e) / (cosh delta + c sinh delta)
 //   dK = (d-1) log(cosh delta + c sinh delta).
 // Returned as u' = A u + Bg g~ so the per-element update is one fma.
-// cosh - 1 is taken as 2 sinh^2(delta/2); beyond |delta| = 20 the quotient is
-// divided through by cosh delta (tanh/sech form) to avoid overflow.
+// Below |delta| = 20 both hyperbolic terms come from one expm1 (no
+// cancellation for small delta); beyond it the quotient is divided through by
+// cosh delta (tanh/sech form) to avoid overflow.
 // ---------------------------------------------------------------------------
 struct BMap {
   double A, Bg, dK;
@@ -155,33 +160,37 @@ __device__ __forceinline__ BMap b_map(double gg, double gu, double h, double dm1
     return r;
   }
   const double n = sqrt(gg);
+  const double in = 1.0 / n;
   const double delta = h * n / dm1;
-  const double c = gu / n;
-  if (fabs(delta) < 20.0) {
-    const double sh = sinh(delta);
-    const double shh = sinh(0.5 * delta);
-    const double chm1 = 2.0 * shh * shh;
+  const double c = gu * in;
+  const double ad = fabs(delta);
+  if (ad < 20.0) {
+    // one expm1 of |delta| gives both hyperbolic terms:
+    // cosh - 1 = E^2 / (2 (E + 1)), sinh = E - (cosh - 1), E = e^|delta| - 1
+    const double E = expm1(ad);
+    const double chm1 = 0.5 * E * E / (E + 1.0);
+    const double sh = copysign(E - chm1, delta);
     const double Dm1 = chm1 + c * sh;
     const double invD = 1.0 / (1.0 + Dm1);
     r.A = invD;
-    r.Bg = (sh + c * chm1) / n * invD;
+    r.Bg = (sh + c * chm1) * in * invD;
     r.dK = dm1 * log1p(Dm1);
   } else {
-    const double ad = fabs(delta);
     const double e2 = exp(-2.0 * ad);
     const double tau = copysign((1.0 - e2) / (1.0 + e2), delta);
     const double sech = 2.0 * exp(-ad) / (1.0 + e2);
     const double Dh = 1.0 + c * tau;
     r.A = sech / Dh;
-    r.Bg = (tau + c * (1.0 - sech)) / n / Dh;
+    r.Bg = (tau + c * (1.0 - sech)) * in / Dh;
     r.dK = dm1 * (ad + log1p(e2) - 0.69314718055994531 + log(Dh));
   }
   return r;
 }
 
 // The same map with the per-chain scalars in float, for the FP32 state: the
-// coefficients only multiply float vectors, and the energy term is returned
-// as a double for the FP64 energy accumulation.
+// coefficients only multiply float vectors (reciprocals from the hardware
+// 1-ulp instruction), and the energy term is returned as a double for the FP64
+// energy accumulation.
 __device__ __forceinline__ BMap b_map_f(double gg, double gu, double h, double dm1) {
   BMap r;
   if (gg == 0.0) {
@@ -190,27 +199,28 @@ __device__ __forceinline__ BMap b_map_f(double gg, double gu, double h, double d
     r.dK = 0.0;
     return r;
   }
-  const float n = sqrtf((float)gg);
-  const float delta = (float)h * n / (float)dm1;
-  const float c = (float)gu / n;
-  if (fabsf(delta) < 20.0f) {
-    const float sh = sinhf(delta);
-    const float shh = sinhf(0.5f * delta);
-    const float chm1 = 2.0f * shh * shh;
+  const float n = __builtin_amdgcn_sqrtf((float)gg);
+  const float in = __builtin_amdgcn_rcpf(n);
+  const float delta = (float)(h / dm1) * n;
+  const float c = (float)gu * in;
+  const float ad = fabsf(delta);
+  if (ad < 20.0f) {
+    const float E = expm1f(ad);
+    const float chm1 = 0.5f * E * E * __builtin_amdgcn_rcpf(E + 1.0f);
+    const float sh = copysignf(E - chm1, delta);
     const float Dm1 = chm1 + c * sh;
-    const float invD = 1.0f / (1.0f + Dm1);
+    const float invD = __builtin_amdgcn_rcpf(1.0f + Dm1);
     r.A = invD;
-    r.Bg = (sh + c * chm1) / n * invD;
+    r.Bg = (sh + c * chm1) * in * invD;
     r.dK = dm1 * (double)log1pf(Dm1);
   } else {
-    const float ad = fabsf(delta);
-    const float e2 = expf(-2.0f * ad);
-    const float tau = copysignf((1.0f - e2) / (1.0f + e2), delta);
-    const float sech = 2.0f * expf(-ad) / (1.0f + e2);
-    const float Dh = 1.0f + c * tau;
-    r.A = sech / Dh;
-    r.Bg = (tau + c * (1.0f - sech)) / n / Dh;
-    r.dK = dm1 * ((double)ad + (double)log1pf(e2) - 0.69314718055994531 + (double)logf(Dh));
+    const float e2 = __expf(-2.0f * ad);
+    const float tau = copysignf((1.0f - e2) * __builtin_amdgcn_rcpf(1.0f + e2), delta);
+    const float sech = 2.0f * __expf(-ad) * __builtin_amdgcn_rcpf(1.0f + e2);
+    const float iDh = __builtin_amdgcn_rcpf(1.0f + c * tau);
+    r.A = sech * iDh;
+    r.Bg = (tau + c * (1.0f - sech)) * in * iDh;
+    r.dK = dm1 * ((double)ad + (double)log1pf(e2) - 0.69314718055994531 - (double)__logf(iDh));
   }
   return r;
 }

@@ -70,6 +70,12 @@ enum KernelKind { KK_INIT = 0, KK_UNADJ = 1, KK_MAMS_MN2 = 2, KK_MAMS_MN4 = 3, K
 // Local targets: kind is laps_target_kind (gauss, stochvol, phi4).
 hipError_t launch_local(int kind, bool dbl, int Q, KernelKind kk, const LocalArgs &a, int grid, int block,
                         size_t shmem, hipStream_t s);
+hipError_t launch_local_gauss(bool dbl, int Q, KernelKind kk, const LocalArgs &a, int grid, int block, size_t shmem,
+                              hipStream_t s);
+hipError_t launch_local_sv(bool dbl, int Q, KernelKind kk, const LocalArgs &a, int grid, int block, size_t shmem,
+                           hipStream_t s);
+hipError_t launch_local_phi4(bool dbl, int Q, KernelKind kk, const LocalArgs &a, int grid, int block, size_t shmem,
+                             hipStream_t s);
 hipError_t launch_prep_aux(int kind, bool dbl, const void *src, void *aux, int64_t d, int64_t ld, hipStream_t s);
 // Per-dimension ensemble sums of (x - K, (x - K)^2, (x - K) g, g) over CB
 // chain blocks, one partial row per block (used when the step kernel does not

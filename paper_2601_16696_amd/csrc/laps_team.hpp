@@ -50,9 +50,11 @@ __device__ __forceinline__ void load_row(const Real *row, int r, int T, int64_t 
     const int64_t e0 = 8 * (int64_t)(r + q * T);
     if (act && e0 < d) {
       ld8<Real>(row + e0, v[q]);
+      if (e0 + 8 > d) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (e0 + i >= d) v[q][i] = Real(0);
+        for (int i = 0; i < 8; ++i)
+          if (e0 + i >= d) v[q][i] = Real(0);
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[q][i] = Real(0);
@@ -88,12 +90,30 @@ __device__ __forceinline__ void lane_normals(uint64_t seed, uint64_t m, int r, i
   }
 }
 
+// Standard normals of one oct (zero beyond d), generated where they are
+// consumed so that no [Q][8] array of them stays live.
+template <class Real>
+__device__ __forceinline__ void oct_normals(uint64_t seed, uint64_t m, int64_t oct, int64_t d, uint64_t t,
+                                            uint32_t tag, uint32_t sub, Real (&z)[8]) {
+  if (8 * oct < d) {
+    normals8<Real>(seed, m, (uint64_t)oct, t, tag, sub, z);
+    if (8 * oct + 8 > d) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (8 * oct + i >= d) z[i] = Real(0);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = Real(0);
+  }
+}
+
 // Per-dimension sums over every chain this workgroup visited, written as one
 // partial row per workgroup: teams inside a wavefront are combined by xor
 // butterflies, wavefronts in a fixed order through LDS.
 template <class Real, int Q>
 __device__ __forceinline__ void write_partials(double *partials, int64_t d, int64_t ld, double (&S)[4][Q][8],
-                                               double *red, int T, int r) {
+                                               double *buf, int T, int r) {
   double *P = partials + (size_t)blockIdx.x * 4 * ld;
   if ((int)blockDim.x == T) {
 #pragma unroll
@@ -121,7 +141,6 @@ __device__ __forceinline__ void write_partials(double *partials, int64_t d, int6
   const int groups = blockDim.x / (T < 64 ? 64 : T);
   const int grp = threadIdx.x / (T < 64 ? 64 : T);
   const int lig = threadIdx.x - grp * (T < 64 ? 64 : T);  // lane index inside its group
-  double *buf = red + 2 * kRedSlots;                       // after the reduction slots
   const int span = 8 * Q * lanes;
   for (int gI = 0; gI < groups; ++gI) {
     if (grp == gI && lig < lanes) {

@@ -75,6 +75,30 @@ def _small_workloads():
     }
 
 
+# Team shapes of the per-chain kernels, forced through team_lanes so that the
+# small sizes above reach every code path: several octs per lane (Q > 1, the
+# column-sum statistics), octs wrapping across lanes in the neighbour exchange,
+# the whole-oct lattice rows (side a multiple of 8) and multi-wavefront teams.
+SHAPES = {
+    # name: (workload, {precision: team_lanes})
+    "gauss": ("gauss", {"f64": 0, "f32": 0}),                        # 16 lanes x 1 oct
+    "gauss_q2": ("gauss", {"f64": 8, "f32": 4}),                     # 2 / 4 octs per lane
+    "stochvol": ("stochvol", {"f64": 0, "f32": 0}),                  # 32 lanes x 1 oct
+    "stochvol_q": ("stochvol", {"f64": 16, "f32": 8}),               # 2 / 4 octs per lane
+    "stochvol_multiwave": ("stochvol", {"f64": 128, "f32": 128}),    # two wavefronts per chain
+    "phi4": ("phi4", {"f64": 0, "f32": 0}),                          # side 12: per-site neighbours
+    "phi4_rows": ("phi4_multiwave", {"f64": 0, "f32": 0}),           # side 32: 64 lanes x 2 octs
+    "phi4_rows_q": ("phi4_multiwave", {"f64": 64, "f32": 32}),       # 2 / 4 octs per lane
+    "phi4_multiwave": ("phi4_multiwave", {"f64": 128, "f32": 128}),  # two wavefronts per chain
+    "gauss_d3": ("gauss_d3", {"f64": 0, "f32": 0}),
+}
+
+
+def _shape(name, prec):
+    wname, lanes = SHAPES[name]
+    return _small_workloads()[wname], {"team_lanes": lanes[prec]}
+
+
 @pytest.mark.parametrize("name", ["gauss", "stochvol", "phi4", "phi4_multiwave", "gauss_d3"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_target_eval(gpu, orc, name, prec):
@@ -136,10 +160,10 @@ def _compare_x(o, s, prec):
     assert np.max(err) < TOL[prec], np.max(err)
 
 
-@pytest.mark.parametrize("name", ["gauss", "stochvol", "phi4", "phi4_multiwave", "gauss_d3"])
+@pytest.mark.parametrize("name", list(SHAPES))
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_unadjusted_steps(gpu, orc, name, prec):
-    w = _small_workloads()[name]
+    w, shape = _shape(name, prec)
     replay = prec == "f32"
 
     # d = 3: the velocity energy (d-1) log(cosh delta + c sinh delta) is
@@ -171,7 +195,7 @@ def test_unadjusted_steps(gpu, orc, name, prec):
             for key in ("L", "dtilde"):
                 assert _close(sg[key], so[key], TOL[prec]), (k, key, sg[key], so[key])
 
-    o, s = _run_pair(gpu, orc, w, prec, 30, replay, per_step=check, switch_policy=1, max_steps_unadj=1000)
+    o, s = _run_pair(gpu, orc, w, prec, 30, replay, per_step=check, switch_policy=1, max_steps_unadj=1000, **shape)
     tol = TOL[prec] if per_step_delta or prec == "f32" else 1e-8
     x = s.positions().cpu().numpy()
     assert np.max(_rel_rows(x, o.array("x"))) < tol, np.max(_rel_rows(x, o.array("x")))
@@ -179,15 +203,17 @@ def test_unadjusted_steps(gpu, orc, name, prec):
     assert np.max(_rel_rows(u, o.array("u"))) < tol
 
 
-@pytest.mark.parametrize("name", ["gauss", "stochvol", "phi4"])
+@pytest.mark.parametrize("name", ["gauss", "gauss_q2", "stochvol", "stochvol_q", "stochvol_multiwave", "phi4",
+                                  "phi4_rows", "phi4_rows_q", "phi4_multiwave"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_adjusted_transitions(gpu, orc, name, prec):
     """MAMS transitions after a fixed switch.  Chains whose accept decision
     differs between GPU and oracle (U within rounding of e^{-Delta}) are
     counted; FP64 allows none."""
-    w = _small_workloads()[name]
+    w, shape = _shape(name, prec)
     replay = prec == "f32"
-    o, s = _run_pair(gpu, orc, w, prec, 12, replay, switch_policy=1, max_steps_unadj=12, max_steps_total=400)
+    o, s = _run_pair(gpu, orc, w, prec, 12, replay, switch_policy=1, max_steps_unadj=12, max_steps_total=400,
+                     **shape)
     assert o.stats()["phase"] == s.stats()["phase"] == 1
     flipped = np.zeros(w["n_chains"], dtype=bool)
     for k in range(4):
