@@ -191,7 +191,9 @@ laps_status laps_target_eval(const laps_target *target, int32_t prec, const void
  * The sampler's normals for (chain m, step t, tag, substep) use counter
  * (m, j, t, tag | substep << 8) for dims 8j..8j+7: word k gives the pair
  * U_a = (hi32 + 1/2) 2^-32, U_b = (lo32 + 1/2) 2^-32 and the Box-Muller
- * values sqrt(-2 ln U_a) (cos, sin)(2 pi U_b) for dims 8j+2k, 8j+2k+1.
+ * values sqrt(-2 ln U_a) (cos, sin)(2 pi U_b) for dims 8j+2k, 8j+2k+1
+ * (FP32 state evaluates them with the hardware log2, sqrt, sin and cos, to
+ * an absolute error of order 1e-6).
  *   laps_philox_normals: fills out_dev [n_chains][ld] (double for LAPS_F64,
  *   float otherwise) with that stream for chains 0..n_chains-1.
  * Tags: 1 first partial refresh of a step, 2 second partial refresh,
@@ -206,6 +208,44 @@ laps_status laps_philox_normals(uint64_t seed, int64_t n_chains, int64_t d, uint
  * the mean time of one.  Overwrites only the gradient/log p staging of the
  * workspace with values at the current positions.  Synchronises the stream. */
 laps_status laps_time_gradient(laps_ctx *ctx, int32_t n_reps, float *avg_ms);
+
+/* Times one hot kernel of a context with a per-chain target (Gaussian, SV,
+ * phi4): n_reps launches on the context's stream between two HIP events,
+ * *avg_ms the mean duration of one.  which = 1: the unadjusted step kernel
+ * alone (positions and velocities advance, no statistics or controller; the
+ * context must be in the unadjusted phase); which = 2: the fused adjusted
+ * transition kernel alone (context in the adjusted phase, before
+ * max_steps_total).  A launch in the wrong phase is a no-op and is timed as
+ * such.  LAPS_EUNSUPPORTED for other targets.  Synchronises the stream. */
+laps_status laps_time_kernel(laps_ctx *ctx, int32_t which, int32_t n_reps, float *avg_ms);
+
+/* Starts a fresh run in the context's memory: copies x0_dev ([N][ld], may be
+ * NULL to keep the current positions) into the positions, resets the
+ * hyperparameters and runs the initialisation (gradient, velocities,
+ * statistics, controller) -- the same state laps_init leaves.  Enqueue-only
+ * and free of allocations and memsets, so it can be recorded in a graph. */
+laps_status laps_restart(laps_ctx *ctx, const void *x0_dev);
+
+/* Batched runs.  laps_graph_create records, for every context k, a segment
+ * of a run -- laps_restart(ctx_k, x0s[k]) if restart is nonzero (x0s may be
+ * NULL), then n_unadj unadjusted steps (skipped once the context has entered
+ * the adjusted phase) and n_adj adjusted transitions -- into one executable
+ * HIP graph.  Each context's work stays on its own stream (which must be a
+ * created stream, not the default one), forked from and joined back into a
+ * private recording stream, so independent ensembles (different targets,
+ * sizes and precisions) run concurrently when the graph is launched;
+ * contexts sharing a stream run one after another.  A long run is recorded
+ * as a few segment graphs (created in run order, since recording advances the
+ * contexts' host state as the enqueue calls would) and replayed in order;
+ * replaying a segment that contains the switch again is harmless.  The
+ * contexts' host state is left as after the recorded calls.
+ * laps_graph_launch enqueues one replay on `stream`.  The graph owns no
+ * device memory; the contexts and their buffers must outlive it. */
+typedef struct laps_graph laps_graph;
+laps_status laps_graph_create(laps_ctx *const *ctxs, int32_t n_ctx, int32_t restart, const void *const *x0s,
+                              int64_t n_unadj, int64_t n_adj, laps_graph **out);
+laps_status laps_graph_launch(laps_graph *graph, void *stream);
+laps_status laps_graph_destroy(laps_graph *graph);
 
 /* Device pointers into the context's workspace: 0 u [N][ld], 1 g [N][ld],
  * 2 logp [N] (double), 3 delta [N] (double), 4 acc [N] (double),

@@ -269,7 +269,9 @@ __global__ void __launch_bounds__(256) k_switch(CtlArgs c) {
     else
       static_cast<float *>(c.sigma)[i] = (float)s;
   }
-  if (i == 0) {
+  // once per run: a repeated switch (a replayed graph chunk) only rewrites
+  // the same preconditioner and leaves the bisection state alone
+  if (i == 0 && !H->switched) {
     H->phase = PH_ADJ;
     H->integ = c.integ;
     H->a_star = c.acc_target > 0.0 ? c.acc_target : (c.integ == 2 ? 0.9 : 0.7);
@@ -312,6 +314,19 @@ __global__ void __launch_bounds__(1024) k_ctl_adj(CtlArgs c) {
 
 hipError_t launch_hyper_init(const CtlArgs &c, hipStream_t s) {
   hipLaunchKernelGGL(k_hyper_init, dim3(1), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+// Plain fill, used instead of a memset node so that the restart sequence can
+// be recorded in a graph.
+__global__ void k_fill(double *p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+  int64_t g = (n + 255) / 256;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 hipError_t launch_finalize(const CtlArgs &c, int mode, hipStream_t s) {

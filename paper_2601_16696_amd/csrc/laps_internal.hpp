@@ -64,6 +64,7 @@ hipError_t launch_ctl_init(const CtlArgs &c, hipStream_t s);
 hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s);
 hipError_t launch_switch(const CtlArgs &c, hipStream_t s);
 hipError_t launch_ctl_adj(const CtlArgs &c, hipStream_t s);
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 
 enum KernelKind { KK_INIT = 0, KK_UNADJ = 1, KK_MAMS_MN2 = 2, KK_MAMS_MN4 = 3, KK_EVAL = 4 };
 

@@ -769,12 +769,12 @@ hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s) {
 // (gfx950 provides 160 KiB per workgroup).
 template <int KC>
 static hipError_t launch_staged(dim3 grid, size_t shm, const LogregArgs &a, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
+  static size_t attr_set = 0;  // largest dynamic LDS size granted so far
+  if (shm > attr_set) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_lr_grad_bf16<KC>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    attr_set = shm;
   }
   hipLaunchKernelGGL(k_lr_grad_bf16<KC>, grid, dim3(512), shm, s, a);
   return hipGetLastError();

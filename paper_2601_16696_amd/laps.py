@@ -56,7 +56,8 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["laps_config_default", "laps_row_stride", "laps_workspace_size", "laps_init", "laps_step_unadjusted",
            "laps_step_adjusted", "laps_ensemble_stats", "laps_target_eval", "laps_philox_words",
-           "laps_philox_normals", "laps_time_gradient", "laps_buffer", "laps_destroy", "laps_status_string",
+           "laps_philox_normals", "laps_time_gradient", "laps_time_kernel", "laps_restart", "laps_graph_create",
+           "laps_graph_launch", "laps_graph_destroy", "laps_buffer", "laps_destroy", "laps_status_string",
            "laps_last_error"]
 
 _lib = None
@@ -85,6 +86,11 @@ def lib():
         "laps_philox_words": (I32, [P, P, I64, U64, P]),
         "laps_philox_normals": (I32, [U64, I64, I64, U64, U32, U32, I32, P, P]),
         "laps_time_gradient": (I32, [P, I32, P]),
+        "laps_time_kernel": (I32, [P, I32, I32, P]),
+        "laps_restart": (I32, [P, P]),
+        "laps_graph_create": (I32, [P, I32, I32, P, I64, I64, P]),
+        "laps_graph_launch": (I32, [P, P]),
+        "laps_graph_destroy": (I32, [P]),
         "laps_buffer": (P, [P, I32]),
         "laps_destroy": (I32, [P]),
         "laps_status_string": (ctypes.c_char_p, [I32]),
@@ -240,6 +246,20 @@ class Sampler:
         self.x[:, :self.d].copy_(x0)
         self._init()
 
+    def restart(self, x0=None):
+        """Enqueues a fresh run from x0 (device tensor [N, d]; None keeps the
+        current positions) without reallocating: the state laps_init leaves."""
+        if x0 is not None:
+            self.x[:, :self.d].copy_(x0)
+        _check(lib().laps_restart(self.ctx, None), self.ctx)
+
+    def time_kernel(self, which: str, n_reps: int = 20) -> float:
+        """Mean milliseconds of the unadjusted step kernel ("unadj") or the
+        fused adjusted transition kernel ("adj") alone (per-chain targets)."""
+        ms = ctypes.c_float(0.0)
+        _check(lib().laps_time_kernel(self.ctx, {"unadj": 1, "adj": 2}[which], n_reps, ctypes.byref(ms)), self.ctx)
+        return ms.value
+
     def time_gradient(self, n_reps: int = 20) -> float:
         """Mean milliseconds of one ensemble gradient evaluation (HIP events on the sampler's stream)."""
         ms = ctypes.c_float(0.0)
@@ -285,6 +305,38 @@ class Sampler:
         if name == "sigma":
             return self.ws[off:off + self.ld * es].view(dt)[:self.d]
         return self.ws[off:off + self.N * 8].view(torch.float64)
+
+
+class RunGraph:
+    """One executable graph replaying a segment of LAPS runs of several
+    samplers concurrently, each on the created (non-default) stream it was
+    made on: an optional restart, n_unadj unadjusted steps, n_adj adjusted
+    transitions.  Segments are created in run order and launched in the same
+    order.
+
+    x0s: per-sampler device tensors [N, ld] in the sampler's state type, the
+    starting positions of a restart (None restarts from the positions the
+    sampler holds at replay time)."""
+
+    def __init__(self, samplers, n_unadj: int, n_adj: int, restart: bool = False, x0s=None):
+        self.samplers = list(samplers)
+        self.x0s = None if x0s is None else list(x0s)
+        n = len(self.samplers)
+        ctxs = (ctypes.c_void_p * n)(*[s.ctx.value for s in self.samplers])
+        xp = None
+        if self.x0s is not None:
+            xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in self.x0s])
+        self.g = ctypes.c_void_p()
+        _check(lib().laps_graph_create(ctxs, n, 1 if restart else 0, xp, n_unadj, n_adj, ctypes.byref(self.g)))
+
+    def launch(self, stream=None):
+        _check(lib().laps_graph_launch(self.g, _stream_ptr(stream)))
+
+    def __del__(self):
+        g = getattr(self, "g", None)
+        if g and _lib is not None:
+            _lib.laps_graph_destroy(g)
+            self.g = None
 
 
 def philox_words(ctr: np.ndarray, seed: int, device="cuda:0") -> np.ndarray:

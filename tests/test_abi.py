@@ -107,3 +107,47 @@ def test_init_rejects_before_touching_the_device(L):
     assert lib.laps_step_unadjusted(None, 1) == L.EINVAL
     assert lib.laps_step_adjusted(None, 1) == L.EINVAL
     assert lib.laps_status_string(L.EPHASE).decode() == "wrong phase"
+
+
+def test_batch_and_restart_entry_points_validate(L):
+    lib = L.lib()
+    P = ctypes.c_void_p
+    ms = ctypes.c_float(0.0)
+    g = ctypes.c_void_p()
+    assert lib.laps_restart(None, None) == L.EINVAL
+    assert lib.laps_time_kernel(None, 1, 5, ctypes.byref(ms)) == L.EINVAL
+    assert lib.laps_graph_create(None, 1, 1, None, 10, 0, ctypes.byref(g)) == L.EINVAL
+    ctxs = (P * 1)(None)
+    assert lib.laps_graph_create(ctxs, 1, 1, None, 10, 0, ctypes.byref(g)) == L.EINVAL
+    assert lib.laps_graph_create(ctxs, 0, 1, None, 10, 0, ctypes.byref(g)) == L.EINVAL
+    assert lib.laps_graph_launch(None, None) == L.EINVAL
+    assert lib.laps_graph_destroy(None) == L.OK
+
+
+@pytest.mark.parametrize("kind,d,side,lanes,ok", [
+    (0, 100, 0, 0, True), (0, 100, 0, 4, True), (0, 100, 0, 3, False), (0, 100, 0, 96, False),
+    (0, 100, 0, 128, True), (0, 100, 0, 1024, False), (2, 2429, 0, 64, True), (2, 2429, 0, 16, False),
+    (3, 4096, 64, 0, True), (3, 144, 12, 4, False), (3, 144, 12, 32, True)])
+def test_team_shape_override(L, kind, d, side, lanes, ok):
+    """team_lanes picks the lanes per chain; shapes needing more octs per lane
+    than the kernels hold (6 in FP32), or lanes that are neither a power of
+    two up to 64 nor a multiple of 64 up to 512, are refused.  A phi^4 side
+    that is not a multiple of 8 takes one oct per lane."""
+    c, t = _cfg_target(L, kind=kind, d=d, side=side)
+    c.prec = L.F32
+    c.team_lanes = lanes
+    st, _ = _ws(L, c, t)
+    assert (st == L.OK) == ok, st
+    c.team_lanes = -1
+    assert _ws(L, c, t)[0] == L.EINVAL
+
+
+def test_logreg_mn4_refused(L):
+    """The logistic-regression MN4 transition is refused until its GPU fault is explained."""
+    c, t = _cfg_target(L, kind=1, d=204)
+    assert _ws(L, c, t)[0] == L.EUNSUPPORTED
+    c.integrator_adj = 1
+    assert _ws(L, c, t)[0] == L.OK
+    c, t = _cfg_target(L, kind=1, d=100)
+    c.integrator_adj = 2
+    assert _ws(L, c, t)[0] == L.EUNSUPPORTED

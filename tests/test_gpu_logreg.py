@@ -47,7 +47,7 @@ def _rel_rows(a, b):
 def test_gradient_at_init_f64(gpu, orc, shape):
     N, n, d = shape
     w = _w(N, n, d)
-    s = gpu.Sampler(w, "f64")
+    s = gpu.Sampler(w, "f64", integrator_adj=1)
     s.stats()
     g = s.buffer("g").cpu().numpy()
     lp = s.buffer("logp").cpu().numpy()
@@ -59,11 +59,21 @@ def test_gradient_at_init_f64(gpu, orc, shape):
     assert np.max(_rel_rows(g, gref)) < 1e-12
 
 
-@pytest.mark.parametrize("shape", [(100, 300, 37), (64, 32, 100), (130, 5000, 100), (40, 77, 300)])
+# (n, d) of the batched mix's logistic targets reach every k-chunk count of the
+# staged (d <= 128) and direct-load gradient kernels; fewer chains, with n
+# shortened where the oracle would be slow
+C5_LR = [(48, 1000, 20), (40, 1534, 29), (36, 2354, 43), (24, 3611, 64), (20, 2000, 94), (16, 1200, 138),
+         (12, 800, 204), (8, 600, 300)]
+# d > 200 would select MN4, which is refused for this target (see test_fourth_order_transitions); the
+# gradient kernels at those d are checked with the MN2 integrator requested explicitly
+MN2 = dict(integrator_adj=1)
+
+
+@pytest.mark.parametrize("shape", [(100, 300, 37), (64, 32, 100), (130, 5000, 100), (40, 77, 300)] + C5_LR)
 def test_gradient_at_init_bf16_error_bounds(gpu, orc, shape):
     N, n, d = shape
     w = _w(N, n, d)
-    s = gpu.Sampler(w, "bf16")
+    s = gpu.Sampler(w, "bf16", **MN2)
     s.stats()
     th = np.asarray(w["x0"], dtype=np.float32).astype(np.float64)  # the FP32 state
     g = s.buffer("g").cpu().numpy().astype(np.float64)
@@ -139,3 +149,39 @@ def test_mixed_adjusted_runs_and_accepts(gpu, orc):
     assert st["phase"] == 2 and st["n_nonfinite"] == 0
     assert abs(st["acc_mean"] - 0.7) < 0.15
     assert np.all(np.isfinite(s.positions().cpu().numpy()))
+
+
+@pytest.mark.skip(reason="the logistic-regression MN4 transition faulted the GPU (illegal memory access) with no "
+                         "cause shown yet; the library refuses that configuration until one is")
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+def test_fourth_order_transitions(gpu, orc, prec):
+    """d > 200 selects the MN4 integrator for the adjusted phase: five
+    gradient stages per step through the per-chain update kernel.  FP64
+    against the oracle at 1e-10; bf16 with the oracle replaying eps."""
+    w = _w(40, 150, 204, seed=5)
+    cfg = dict(switch_policy=1, max_steps_unadj=8, max_steps_total=8 + 15 * 3)
+    o = _oracle(orc, w, **cfg)
+    s = gpu.Sampler(w, prec, **cfg)
+    replay = prec != "f64"
+    for _ in range(8):
+        if replay:
+            sg = s.stats()
+            o.set_hyper(sg["eps"], sg["L"])
+        o.step_unadjusted(1)
+        s.step_unadjusted(1)
+    for k in range(2):
+        if replay and k > 0:
+            o.set_hyper(s.stats()["eps"], 0.0)
+        o.step_adjusted(1)
+        s.step_adjusted(1)
+        so, sg = o.stats(), s.stats()
+        assert so["integrator"] == sg["integrator"] == 2 and so["t"] == sg["t"]
+        assert sg["n_nonfinite"] == 0
+    x, xo = s.positions().cpu().numpy(), o.array("x")
+    err = _rel_rows(x, xo)
+    if prec == "f64":
+        assert np.max(err) < 1e-10, np.max(err)
+        np.testing.assert_allclose(s.buffer("acc").cpu().numpy(), o.array("acc"), rtol=0, atol=1e-8)
+    else:
+        # chains whose accept decision flips between the two (U within the bf16 energy error) are excluded
+        assert np.mean(err > 1e-2) <= 0.1 and np.max(err[err <= 1e-2]) < 2e-3, (np.mean(err > 1e-2), np.max(err))
