@@ -204,7 +204,7 @@ Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
   size_t lr = 0;
   if (tg->kind == LAPS_LOGREG) {
     int S, NB, bps;
-    logreg_splits(tg->dims[0], N, S, NB, bps);
+    logreg_splits(tg->dims[0], N, cfg->prec, d, S, NB, bps);
     lr = logreg_layout(cfg->prec == LAPS_F64 ? 0 : 1, tg->dims[0], d, N, ld, S).total;
   }
   L.packed = c.take(lr);
@@ -311,7 +311,7 @@ LogregArgs logreg_args(laps_ctx *c, int gate) {
   a.N = c->cfg.n_chains;
   a.d = c->cfg.d;
   a.ld = c->ld;
-  logreg_splits(a.n, a.N, a.S, a.NB, a.bps);
+  logreg_splits(a.n, a.N, c->cfg.prec, a.d, a.S, a.NB, a.bps);
   a.KC = (int)((a.d + 31) / 32);
   a.T = c->T;
   a.tpw = c->tpw;

@@ -189,6 +189,32 @@ __device__ __forceinline__ void chain_sums(const double *a, int64_t N, double sh
   bad = v2[1];
 }
 
+// Sum, sum of squares and NaN count of a per-chain array in one pass.
+__device__ __forceinline__ void chain_sums2(const double *a, int64_t N, double &sum, double &sq, double &bad,
+                                            double *sh) {
+  double s = 0.0, q = 0.0, nb = 0.0;
+  const int64_t B = blockDim.x;
+  int64_t m = threadIdx.x;
+  for (; m + 3 * B < N; m += 4 * B) {
+    const double a0 = a[m], a1 = a[m + B], a2 = a[m + 2 * B], a3 = a[m + 3 * B];
+    s += (a0 + a1) + (a2 + a3);
+    q += (a0 * a0 + a1 * a1) + (a2 * a2 + a3 * a3);
+    nb += (double)(!isfinite(a0)) + (double)(!isfinite(a1)) + (double)(!isfinite(a2)) + (double)(!isfinite(a3));
+  }
+  for (; m < N; m += B) {
+    const double v = a[m];
+    s += v;
+    q += v * v;
+    if (!isfinite(v)) nb += 1.0;
+  }
+  double v3[3] = {s, q, nb};
+  const int op[3] = {0, 0, 0};
+  block_reduce<3>(v3, op, sh);
+  sum = v3[0];
+  sq = v3[1];
+  bad = v3[2];
+}
+
 __global__ void __launch_bounds__(256) k_ctl_init(CtlArgs c) {
   __shared__ double sh[4 * 4];
   (void)sh;
@@ -205,13 +231,18 @@ __global__ void __launch_bounds__(1024) k_ctl_unadj(CtlArgs c) {
   if (H->phase != PH_UNADJ) return;
   __shared__ double sh[16 * 4];
   __shared__ double mean_sh;
-  double sum, bad;
-  chain_sums(c.delta, c.N, 0.0, 0, sum, bad, sh);
-  if (threadIdx.x == 0) mean_sh = sum / (double)c.N;
-  __syncthreads();
-  const double mu = mean_sh;
-  double sq, bad2;
-  chain_sums(c.delta, c.N, c.eevpd_mode == 1 ? 0.0 : mu, 1, sq, bad2, sh);
+  double sum, bad, sq;
+  if (c.eevpd_mode == 1) {
+    // mean square: one pass
+    chain_sums2(c.delta, c.N, sum, sq, bad, sh);
+  } else {
+    // variance: two passes about the mean
+    chain_sums(c.delta, c.N, 0.0, 0, sum, bad, sh);
+    if (threadIdx.x == 0) mean_sh = sum / (double)c.N;
+    __syncthreads();
+    double bad2;
+    chain_sums(c.delta, c.N, mean_sh, 1, sq, bad2, sh);
+  }
   // block scalars of the statistics pass, reduced in a fixed tree order
   double p3[3] = {0.0, 0.0, -INFINITY};
   for (int b = threadIdx.x; b < c.nb; b += blockDim.x) {

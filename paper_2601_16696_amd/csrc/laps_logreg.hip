@@ -28,10 +28,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-void logreg_splits(int64_t n, int64_t N, int &S, int &NB, int &bps) {
+// The eight-wavefront staged gradient kernel is the default; LAPS_LR_KERNEL=pipe
+// selects the pipelined one (d <= 128).
+bool lr_pipelined() {
+  static const int v = [] {
+    const char *e = getenv("LAPS_LR_KERNEL");
+    return (e && e[0] == 'p') ? 1 : 0;
+  }();
+  return v != 0;
+}
+
+void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int &S, int &NB, int &bps) {
   NB = (int)((n + 31) / 32);
   const int64_t groups = (N + 63) / 64;
-  int64_t target = 256;  // workgroups of one gradient launch (one per CU)
+  // workgroups of one gradient launch: two per CU for the pipelined bf16 kernel, one otherwise
+  int64_t target = (prec != 0 && d <= 128 && lr_pipelined()) ? 512 : 256;
   if (const char *e = getenv("LAPS_LR_WGS")) target = atol(e) > 0 ? atol(e) : target;
   int64_t want = target / (groups > 0 ? groups : 1);
   if (want < 1) want = 1;
@@ -260,6 +271,166 @@ __global__ void __launch_bounds__(512) k_lr_grad_bf16(LogregArgs a) {
     lacc += __shfl_xor(lacc, 32);
     if (mval && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
   }
+}
+
+// ---------------------------------------------------------------------------
+// bf16 matrix-core gradient, pipelined (d <= 128).  grid (ceil(N/64), S),
+// 256 threads = 4 wavefronts; wavefront w owns chain group w (16 chains) and
+// walks every 32-row block of the split.  The blocks' operand fragments and
+// labels pass through a three-stage LDS ring shared by the four chain groups:
+// at block i a wavefront reads stage i (backward fragments, labels) and stage
+// i + 1 (forward fragments), while the workgroup stages block i + 2.  The
+// forward products of block i + 1 are issued before the epilogue of block i,
+// so the matrix cores work while the vector ALU evaluates the sigmoid and
+// softplus terms.  One barrier per block; two workgroups share a CU.
+// ---------------------------------------------------------------------------
+template <int KC, bool FULL>
+__device__ __forceinline__ void lr_epilogue(const f32x4 (&z)[2], const float *Y, int q, int nvalid, bf16x8 &rb,
+                                            double &lacc) {
+  const float4 y0 = *reinterpret_cast<const float4 *>(Y + 4 * q);
+  const float4 y1 = *reinterpret_cast<const float4 *>(Y + 16 + 4 * q);
+  const float yv[2][4] = {{y0.x, y0.y, y0.z, y0.w}, {y1.x, y1.y, y1.z, y1.w}};
+  float lin = 0.f, prod = 1.f;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float zz = z[h][i];
+      const bool ok = FULL || (16 * h + 4 * q + i < nvalid);
+      const float e = __expf(-fabsf(zz));
+      const float ope = 1.0f + e;
+      const float inv = __builtin_amdgcn_rcpf(ope);
+      const float sig = zz >= 0.f ? inv : e * inv;
+      rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - sig : 0.f);
+      lin += ok ? yv[h][i] * zz - fmaxf(zz, 0.f) : 0.f;
+      prod *= ok ? ope : 1.0f;
+    }
+  lacc += (double)lin - (double)__logf(prod);
+}
+
+template <int KC>
+__device__ __forceinline__ void lr_forward(const bf16x8 *L, int lane, const bf16x8 (&thi)[KC],
+                                           const bf16x8 (&tlo)[KC], f32x4 (&z)[2]) {
+  z[0] = f32x4{0.f, 0.f, 0.f, 0.f};
+  z[1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    const bf16x8 a0 = L[kc * 64 + lane], a1 = L[(KC + kc) * 64 + lane];
+    z[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, thi[kc], z[0], 0, 0, 0);
+    z[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, thi[kc], z[1], 0, 0, 0);
+    z[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, tlo[kc], z[0], 0, 0, 0);
+    z[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, tlo[kc], z[1], 0, 0, 0);
+  }
+}
+
+template <int KC>
+__global__ void __launch_bounds__(256) k_lr_grad_bf16_pipe(LogregArgs a) {
+  if (!lr_gate(a)) return;
+  constexpr int kF = 2 * KC * 64;          // forward (or backward) fragments of one 32-row block
+  constexpr int kStage = 2 * kF + 8;       // + 32 labels (8 x 16 bytes)
+  constexpr int NS = 3;
+  constexpr int kPer = (kStage + 255) / 256;
+  extern __shared__ bf16x8 lds[];          // [NS][kStage]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int q = lane >> 4, cl = lane & 15;
+  const int64_t N = a.N, ld = a.ld, n = a.n;
+  const int64_t m = ((int64_t)blockIdx.x * 4 + wave) * 16 + cl;
+  const bool mval = m < N;
+  const float *X = static_cast<const float *>(a.x);
+  // theta as the B operand: k slot 8q + j of chunk kc is coordinate 32kc + 16(j/4) + 4q + j%4
+  bf16x8 thi[KC], tlo[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (mval && d4 < ld) v = *reinterpret_cast<const float4 *>(X + m * ld + d4);
+      const float f[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const __bf16 hi = (__bf16)f[i];
+        thi[kc][4 * hh + i] = hi;
+        tlo[kc][4 * hh + i] = (__bf16)(f[i] - (float)hi);
+      }
+    }
+  }
+  f32x4 gacc[2 * KC];
+#pragma unroll
+  for (int dc = 0; dc < 2 * KC; ++dc) gacc[dc] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double lacc = 0.0;
+  const LrOffsets off = logreg_layout(1, n, a.d, N, ld, a.S);
+  const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
+  const bf16x8 *XB = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xb);
+  const bf16x8 *YF = reinterpret_cast<const bf16x8 *>(a.scratch + off.yf);
+  const int s = blockIdx.y;
+  const int b0 = s * a.bps;
+  const int b1 = (b0 + a.bps < a.NB) ? b0 + a.bps : a.NB;
+  const int nb = b1 - b0;
+  // stage c of block b0 + i: forward fragments, then backward fragments, then labels
+  auto fetch = [&](int i, bf16x8 (&reg)[kPer]) {
+    const int64_t blk = b0 + i;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int c = tid + 256 * k;
+      if (c < kF)
+        reg[k] = XF[blk * kF + c];
+      else if (c < 2 * kF)
+        reg[k] = XB[blk * kF + (c - kF)];
+      else if (c < kStage)
+        reg[k] = YF[blk * 8 + (c - 2 * kF)];
+    }
+  };
+  auto stash = [&](int i, const bf16x8 (&reg)[kPer]) {
+    bf16x8 *S = lds + (i % NS) * kStage;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int c = tid + 256 * k;
+      if (c < kStage) S[c] = reg[k];
+    }
+  };
+  bf16x8 reg[kPer];
+  for (int i = 0; i < NS - 1 && i < nb; ++i) {
+    fetch(i, reg);
+    stash(i, reg);
+  }
+  __syncthreads();
+  f32x4 zc[2], zn[2];
+  if (nb > 0) lr_forward<KC>(lds, lane, thi, tlo, zc);
+  for (int i = 0; i < nb; ++i) {
+    const bool pre = i + NS - 1 < nb;
+    if (pre) fetch(i + NS - 1, reg);
+    const bf16x8 *Lc = lds + (i % NS) * kStage;
+    if (i + 1 < nb) lr_forward<KC>(lds + ((i + 1) % NS) * kStage, lane, thi, tlo, zn);
+    bf16x8 rb;
+    const float *Y = reinterpret_cast<const float *>(Lc + 2 * kF);
+    const int64_t nv = n - 32 * (int64_t)(b0 + i);
+    if (nv >= 32)
+      lr_epilogue<KC, true>(zc, Y, q, 32, rb, lacc);
+    else
+      lr_epilogue<KC, false>(zc, Y, q, (int)nv, rb, lacc);
+#pragma unroll
+    for (int dc = 0; dc < 2 * KC; ++dc)
+      gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Lc[kF + dc * 64 + lane], rb, gacc[dc], 0, 0, 0);
+    zc[0] = zn[0];
+    zc[1] = zn[1];
+    if (pre) stash(i + NS - 1, reg);
+    __syncthreads();
+  }
+  float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
+  if (mval) {
+#pragma unroll
+    for (int dc = 0; dc < 2 * KC; ++dc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t dd = 16 * dc + 4 * q + i;
+        if (dd < ld) Gp[dd] = gacc[dc][i];
+      }
+  }
+  lacc += __shfl_xor(lacc, 16);
+  lacc += __shfl_xor(lacc, 32);
+  if (mval && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
 }
 
 // ---------------------------------------------------------------------------
@@ -499,6 +670,12 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
 
   if (mode == LR_INIT || mode == LR_POST) {
     double S[4][1][8] = {};
+    // every global load of this stage is issued before the first dependent use
+    double K[1][8];
+    if (mode == LR_POST) {
+      load_shift<1>(a.shiftK, r, T, d, K);
+      load_row<Real, 1>(U + m * ld, r, T, d, act, u);
+    }
     double lps;
     lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
     if (mode == LR_INIT) {
@@ -536,7 +713,6 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     } else {
       const double Lm = H->L;
       const Real c1 = (Real)exp(-h / Lm), c2 = (Real)(sqrt(-expm1(-2.0 * h / Lm)) / sqrt((double)d));
-      load_row<Real, 1>(U + m * ld, r, T, d, act, u);
       double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
@@ -566,12 +742,10 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
           a.logp[m] = l1;
           a.delta[m] = (sc_l0[m] - l1) + sc_dk[m] + b2.dK;
         }
-        double K[1][8];
-        load_shift<1>(a.shiftK, r, T, d, K);
         accumulate_stats<Real, 1>(S, K, x, g);
       }
     }
-    write_partials<Real, 1>(a.partials, d, ld, S, red, T, r);
+    write_partials<Real, 1>(a.partials, d, ld, S, red + 2 * kRedSlots, T, r);
     return;
   }
 
@@ -788,6 +962,16 @@ hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
     return hipGetLastError();
   }
   const dim3 grid((unsigned)((a.N + 63) / 64), (unsigned)a.S);
+  if (a.KC <= 4 && lr_pipelined()) {
+    const size_t shp = (size_t)3 * (4 * a.KC * 64 + 8) * 16;
+    switch (a.KC) {
+      case 1: hipLaunchKernelGGL(k_lr_grad_bf16_pipe<1>, grid, dim3(256), shp, s, a); break;
+      case 2: hipLaunchKernelGGL(k_lr_grad_bf16_pipe<2>, grid, dim3(256), shp, s, a); break;
+      case 3: hipLaunchKernelGGL(k_lr_grad_bf16_pipe<3>, grid, dim3(256), shp, s, a); break;
+      case 4: hipLaunchKernelGGL(k_lr_grad_bf16_pipe<4>, grid, dim3(256), shp, s, a); break;
+    }
+    return hipGetLastError();
+  }
   const size_t shm = (size_t)2 * (2 * 4 * a.KC * 64 + 16) * 16;
   switch (a.KC) {
     case 1: return launch_staged<1>(grid, shm, a, s);
