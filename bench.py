@@ -15,8 +15,8 @@ phi4 (64 x 64 lattice, 2048 chains, FP32), batched (16 targets, 46018 chains,
 run concurrently from recorded segment graphs).
 
 value = chain-gradient evaluations per second over the timed runs.
-roofline: the dominant kernel, timed with HIP events on the stream it runs on
-(logistic regression: the gradient kernel against the bf16 matrix-core peak,
+roofline: the dominant kernel, one launch in ten inside the timed runs bracketed
+by HIP events on the stream it runs on (logistic regression: the gradient kernel against the bf16 matrix-core peak,
 4 n d flops per chain-gradient; per-chain targets: the unadjusted step kernel
 against HBM, its rows of x, u (and g) read and written once per chain).
 time_to_bias: wall-clock and gradients per chain until the squared bias of
@@ -42,15 +42,17 @@ if ROOT not in sys.path:
 METRIC = "chain-grad evals/s & time to bias b²<0.01, mixed/batched vs plain FP64 GPU"
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of k_lr_grad_bf16<4> on the logistic-regression workload, from FETCH_SIZE and
-# WRITE_SIZE counters scaled by what they read for a plain copy of known size (x2.0 and x1.0); kept
-# with the counter summary under profiles/ and reset to None whenever the kernel changes.
-LR_GRAD_TRAFFIC_BYTES = 29.32e6
+# HBM bytes per launch of the bf16 gradient kernel on the logistic-regression workload, from FETCH_SIZE
+# and WRITE_SIZE counters scaled by what they read for a plain copy of known size; kept with the counter
+# summary under profiles/ and reset to None whenever the kernel changes.
+LR_GRAD_TRAFFIC_BYTES = 36.33e6  # k_lr_grad_bf16_lds<4>: 22.40 MB fetched + 13.93 MB written
 N_UNADJ, N_ADJ = 1000, 67
+# the dominant kernel's launches bracketed by HIP events inside the timed runs: one in LOG_EVERY
+LOG_EVERY = int(os.environ.get("LAPS_BENCH_LOG_EVERY", "10"))
 
 
 def _run_once(s, x0, n_unadj, n_adj):
-    s.reinit(x0)
+    s.restart(x0)  # device-side cold start from x0, same workspace
     s.step_unadjusted(n_unadj)
     s.step_adjusted(n_adj)
 
@@ -69,24 +71,35 @@ def _cfg(n_unadj=N_UNADJ, n_adj=N_ADJ):
     return dict(switch_policy=1, max_steps_unadj=n_unadj, max_steps_total=n_unadj + 15 * n_adj)
 
 
-def gpu_throughput(w, prec, steps, warmup, n_unadj=N_UNADJ, n_adj=N_ADJ):
+def gpu_throughput(w, prec, steps, warmup, n_unadj=N_UNADJ, n_adj=N_ADJ, log=None):
+    """Timed full runs.  log names a kernel ("grad" or "unadj") whose every
+    launch inside the timed runs is bracketed by HIP events on the sampler's
+    stream; its mean duration is returned as kernel_ms."""
     import torch
     from paper_2601_16696_amd import laps
     s = laps.Sampler(w, prec, **_cfg(n_unadj, n_adj))
     x0 = torch.as_tensor(w["x0"], device="cuda:0").to(s.x.dtype)
     for _ in range(warmup):
         _run_once(s, x0, n_unadj, n_adj)
+    if log:
+        # every LOG_EVERY-th launch (at most 5 gradients per integrator step of a 15-step trajectory)
+        s.kernel_log(log, steps * (n_unadj + 75 * n_adj) // LOG_EVERY + 1, LOG_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         _run_once(s, x0, n_unadj, n_adj)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    kernel = None
+    if log:
+        n_launch, tot_ms = s.kernel_log_read()
+        s.kernel_log(log, 0)
+        kernel = dict(launches=n_launch, ms=tot_ms / max(n_launch, 1))
     st = s.stats()
     grad_ms = s.time_gradient(50)
     ms = (t1 - t0) / steps * 1e3
     grads = st["grads_per_chain"] * w["n_chains"]
-    return dict(ms=ms, value=grads / (ms * 1e-3), stats=st, grad_ms=grad_ms, sampler=s)
+    return dict(ms=ms, value=grads / (ms * 1e-3), stats=st, grad_ms=grad_ms, kernel=kernel, sampler=s)
 
 
 def step_kernel_times(w, prec, n_reps=20):
@@ -340,16 +353,18 @@ def main():
     prec = args.prec or default_prec
     w = getattr(workloads, gen)()
     N, d = w["n_chains"], w["d"]
-    r = gpu_throughput(w, prec, args.steps, args.warmup)
+    r = gpu_throughput(w, prec, args.steps, args.warmup, log="grad" if args.workload == "logreg" else "unadj")
+    kern = r["kernel"]
     if args.workload == "logreg":
         n = w["X"].shape[0]
         work = 4.0 * n * d * N  # flops of X theta and X^T r per ensemble gradient
         peak = PEAK_BF16_TFLOPS if prec == "bf16" else 78.6
-        achieved = work / (r["grad_ms"] * 1e-3) / 1e12
+        achieved = work / (kern["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma" if prec == "bf16" else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": LR_GRAD_TRAFFIC_BYTES if prec == "bf16" else None,
                 "traffic_unit": "bytes per launch",
-                "kernel": "k_lr_grad_bf16<4>" if prec == "bf16" else "k_lr_grad_f64", "kernel_ms": r["grad_ms"],
+                "kernel": "k_lr_grad_bf16_lds<4>" if prec == "bf16" else "k_lr_grad_f64", "kernel_ms": kern["ms"],
+                "launches_timed": kern["launches"], "isolated_kernel_ms": r["grad_ms"],
                 "algorithmic_flops_per_launch": work}
         precision = ("bf16 matrix-core gradient, fp32 state, fp64 energy error and reductions"
                      if prec == "bf16" else "fp64 throughout")
@@ -359,10 +374,11 @@ def main():
         unadj_ms, adj_ms = step_kernel_times(w, prec)
         rows = 4 if args.workload == "gauss" else 6  # x, u read and written (+ the kept gradient g)
         work = float(rows * rs * d * N)
-        achieved = work / (unadj_ms * 1e-3) / 1e9
+        achieved = work / (kern["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_unadj (unadjusted step)",
-                "kernel_ms": unadj_ms, "algorithmic_bytes_per_launch": work,
+                "kernel_ms": kern["ms"], "launches_timed": kern["launches"], "isolated_kernel_ms": unadj_ms,
+                "algorithmic_bytes_per_launch": work,
                 "adjusted_transition_kernel_ms": adj_ms, "gradient_only_ms": r["grad_ms"]}
         precision = "fp64 throughout" if prec == "f64" else "fp32 state, fp64 energy error and reductions"
         extra = {}

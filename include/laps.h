@@ -219,6 +219,23 @@ laps_status laps_time_gradient(laps_ctx *ctx, int32_t n_reps, float *avg_ms);
  * such.  LAPS_EUNSUPPORTED for other targets.  Synchronises the stream. */
 laps_status laps_time_kernel(laps_ctx *ctx, int32_t which, int32_t n_reps, float *avg_ms);
 
+/* Kernel timing inside ordinary runs: records a pair of HIP events on the
+ * context's stream around every `every`-th launch (the first, then every
+ * every-th after it) of one kernel of the steps that follow, for up to
+ * `capacity` recorded launches.  which: LAPS_KERNEL_UNADJ (per-chain unadjusted
+ * step kernel) or LAPS_KERNEL_MAMS (per-chain MAMS transition kernel) for the
+ * Gaussian, stochastic-volatility and phi^4 targets; LAPS_KERNEL_GRAD (the
+ * gradient kernel, every launch inside unadjusted steps and MAMS
+ * trajectories) for logistic regression; 0 or capacity 0 ends logging.
+ * The events are created without the system-scope fence (timing only).
+ * Synchronises the stream and discards earlier records.  Graph recording
+ * (laps_graph_create) refuses a context that is logging. */
+enum { LAPS_KERNEL_UNADJ = 1, LAPS_KERNEL_MAMS = 2, LAPS_KERNEL_GRAD = 3 };
+laps_status laps_kernel_log(laps_ctx *ctx, int32_t which, int32_t capacity, int32_t every);
+/* Waits for the last logged launch; *count = logged launches, *total_ms =
+ * the sum of their event-to-event durations. */
+laps_status laps_kernel_log_read(laps_ctx *ctx, int64_t *count, double *total_ms);
+
 /* Starts a fresh run in the context's memory: copies x0_dev ([N][ld], may be
  * NULL to keep the current positions) into the positions, resets the
  * hyperparameters and runs the initialisation (gradient, velocities,

@@ -4,6 +4,7 @@
 // laps_ensemble_stats.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -34,6 +35,14 @@ struct laps_ctx {
   void *u, *g, *sigma, *aux, *packed;
   double *logp, *delta, *acc, *partials, *shiftK, *mean, *var, *m2, *Vii, *ring, *wdelta, *part2;
   std::string err;
+  // optional event pairs around the launches of one kernel (laps_kernel_log)
+  int log_which = 0, log_every = 1;
+  int64_t log_seen = 0;  // launches of the logged kernel so far
+  std::vector<hipEvent_t> log_ev;
+  size_t log_used = 0;
+  ~laps_ctx() {
+    for (hipEvent_t e : log_ev) hipEventDestroy(e);
+  }
 };
 
 static std::string g_last_global;
@@ -121,6 +130,11 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape
   // Up to 256 threads per workgroup; fewer when the teams' chain copies would
   // take more than 56 KiB of LDS (which would cap the resident wavefronts).
   int64_t block = T <= 64 ? 256 : T;
+  if (const char *e = getenv("LAPS_LOCAL_BLOCK")) {
+    // workgroup size override (64, 128 or 256 threads) for teams inside a wavefront
+    const int64_t b = atol(e);
+    if (T <= 64 && (b == 64 || b == 128 || b == 256)) block = b;
+  }
   while (T <= 64 && block > T && block > 64 && fixed + body(block) + (size_t)ld * rs > 56 * 1024) block >>= 1;
   s.block = (int)block;
   s.tpw = (int)(block / T);
@@ -373,6 +387,19 @@ laps_status fail(laps_ctx *c, hipError_t e, const char *where) {
     if (e_ != hipSuccess) return fail(ctx, e_, where); \
   } while (0)
 
+// Event-logged launch: records a begin/end event pair around `launch` when
+// kernel `which` is being logged and events remain.
+template <class F>
+hipError_t logged(laps_ctx *c, int which, F &&launch) {
+  bool on = c->log_which == which && c->log_used + 2 <= c->log_ev.size();
+  if (c->log_which == which) on = on && (c->log_seen++ % c->log_every) == 0;
+  hipError_t e = on ? hipEventRecord(c->log_ev[c->log_used], c->stream) : hipSuccess;
+  if (e == hipSuccess) e = launch();
+  if (on && e == hipSuccess) e = hipEventRecord(c->log_ev[c->log_used + 1], c->stream);
+  if (on && e == hipSuccess) c->log_used += 2;
+  return e;
+}
+
 laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
   if (is_local(c->tg.kind)) {
     LocalArgs a = local_args(c);
@@ -382,8 +409,11 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     a.cache = (phase_stats && c->split) ? 1 : 0;
     const int grid = (phase_stats && !c->split) ? c->G : c->grid_full;
     const bool mams = kk == KK_MAMS_MN2 || kk == KK_MAMS_MN4;
-    hipError_t e = launch_local(c->tg.kind, c->dbl, c->Q, kk, a, grid, c->block, mams ? c->shmem_sig : c->shmem,
-                                c->stream);
+    const int which = kk == KK_UNADJ ? LAPS_KERNEL_UNADJ : (mams ? LAPS_KERNEL_MAMS : 0);
+    hipError_t e = logged(c, which, [&] {
+      return launch_local(c->tg.kind, c->dbl, c->Q, kk, a, grid, c->block, mams ? c->shmem_sig : c->shmem,
+                          c->stream);
+    });
     if (e == hipSuccess && phase_stats && c->split)
       e = launch_stats(c->dbl, c->x, c->g, c->shiftK, c->partials, c->cfg.n_chains, c->cfg.d, c->ld, c->G,
                        kk == KK_UNADJ ? c->hyp : nullptr, c->stream);
@@ -394,6 +424,12 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     a.mode = mode;
     a.j = j;
     a.k = k;
+    const Coeffs C = integrator_coeffs(a.integ);
+    a.cK = C.K;
+    a.cb0 = C.b[0];
+    a.ca0 = C.a[0];
+    a.cbk = k + 1 < 6 ? C.b[k + 1] : 0.0;
+    a.cak = k + 1 < 5 ? C.a[k + 1] : 0.0;
     return launch_logreg_update(prec, a, c->G, c->shmem, c->stream);
   };
   hipError_t e = hipSuccess;
@@ -407,7 +443,7 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
   } else if (kk == KK_UNADJ) {
     LogregArgs a = logreg_args(c, 1);
     e = upd(a, LR_PRE, 0, 0);
-    if (e == hipSuccess) e = launch_logreg_grad(prec, a, c->stream);
+    if (e == hipSuccess) e = logged(c, LAPS_KERNEL_GRAD, [&] { return launch_logreg_grad(prec, a, c->stream); });
     if (e == hipSuccess) e = upd(a, LR_POST, 0, 0);
   } else {
     LogregArgs a = logreg_args(c, 2);
@@ -415,7 +451,7 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     e = upd(a, LR_MBEGIN, 0, 0);
     for (int j = 0; j < c->cfg.n_steps_traj && e == hipSuccess; ++j)
       for (int k = 0; k < K - 1 && e == hipSuccess; ++k) {
-        e = launch_logreg_grad(prec, a, c->stream);
+        e = logged(c, LAPS_KERNEL_GRAD, [&] { return launch_logreg_grad(prec, a, c->stream); });
         if (e == hipSuccess) e = upd(a, LR_MSTEP, j, k);
       }
   }
@@ -503,10 +539,10 @@ extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, 
   c->sigma = w + L.sigma;
   c->aux = w + L.aux;
   c->packed = w + L.packed;
-  if (c->shmem_sig > 64 * 1024) {
-    // larger dynamic LDS needs the attribute on every instantiation; this build keeps within 64 KiB
+  if (c->shmem_sig > 160 * 1024) {
+    // a workgroup of gfx950 holds at most 160 KiB of LDS
     delete c;
-    g_last_global = "team shape needs more than 64 KiB of LDS";
+    g_last_global = "team shape needs more than 160 KiB of LDS";
     return LAPS_EUNSUPPORTED;
   }
 
@@ -681,6 +717,10 @@ extern "C" laps_status laps_graph_create(laps_ctx *const *ctxs, int32_t n_ctx, i
       g_last_global = "graph recording needs every context on a created (non-default) stream";
       return LAPS_EINVAL;
     }
+    if (ctxs[k]->log_which != 0) {
+      g_last_global = "graph recording needs kernel event logging off";
+      return LAPS_EINVAL;
+    }
   }
   // recording starts on a private stream; the contexts' streams fork from it
   hipStream_t origin = nullptr;
@@ -825,6 +865,46 @@ extern "C" laps_status laps_time_kernel(laps_ctx *c, int32_t which, int32_t n_re
   hipEventDestroy(e1);
   if (e != hipSuccess) return fail(c, e, "kernel timing");
   *avg_ms = ms / (float)n_reps;
+  return LAPS_OK;
+}
+
+extern "C" laps_status laps_kernel_log(laps_ctx *c, int32_t which, int32_t capacity, int32_t every) {
+  if (!c || capacity < 0 || every < 1 || which < 0 || which > LAPS_KERNEL_GRAD) return LAPS_EINVAL;
+  if (which == LAPS_KERNEL_GRAD ? is_local(c->tg.kind) : (which != 0 && !is_local(c->tg.kind)))
+    return LAPS_EUNSUPPORTED;
+  LAPS_CHECK(c, hipStreamSynchronize(c->stream), "stream sync");
+  for (hipEvent_t e : c->log_ev) hipEventDestroy(e);
+  c->log_ev.clear();
+  c->log_used = 0;
+  c->log_which = 0;
+  c->log_seen = 0;
+  if (which == 0 || capacity == 0) return LAPS_OK;
+  for (int32_t k = 0; k < 2 * capacity; ++k) {
+    hipEvent_t e;
+    // timing-only events: no system-scope cache writeback at each record
+    const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+    if (r != hipSuccess) return fail(c, r, "event");
+    c->log_ev.push_back(e);
+  }
+  c->log_which = which;
+  c->log_every = every;
+  return LAPS_OK;
+}
+
+extern "C" laps_status laps_kernel_log_read(laps_ctx *c, int64_t *count, double *total_ms) {
+  if (!c || !count || !total_ms) return LAPS_EINVAL;
+  *count = 0;
+  *total_ms = 0.0;
+  if (c->log_used == 0) return LAPS_OK;
+  LAPS_CHECK(c, hipEventSynchronize(c->log_ev[c->log_used - 1]), "event sync");
+  double sum = 0.0;
+  for (size_t k = 0; k < c->log_used; k += 2) {
+    float ms = 0.f;
+    LAPS_CHECK(c, hipEventElapsedTime(&ms, c->log_ev[k], c->log_ev[k + 1]), "event time");
+    sum += ms;
+  }
+  *count = (int64_t)(c->log_used / 2);
+  *total_ms = sum;
   return LAPS_OK;
 }
 

@@ -60,6 +60,114 @@ __global__ void k_hyper_init(CtlArgs c) {
   H->switched = 0;
 }
 
+__device__ __forceinline__ double F_bias(double D) {
+  const double r = sqrt(D);
+  return 4.0 * D * r / ((1.0 + r) * (1.0 + r));
+}
+
+// Sum (and NaN count) of a per-chain array over one 256-thread block.
+__device__ __forceinline__ void chain_sums(const double *a, int64_t N, double shiftv, int sq, double &sum,
+                                           double &bad, double *sh) {
+  double s = 0.0, nb = 0.0;
+  int64_t m = threadIdx.x;
+  const int64_t B = blockDim.x;
+  for (; m + 3 * B < N; m += 4 * B) {
+    const double a0 = a[m], a1 = a[m + B], a2 = a[m + 2 * B], a3 = a[m + 3 * B];
+    const double v0 = a0 - shiftv, v1 = a1 - shiftv, v2 = a2 - shiftv, v3 = a3 - shiftv;
+    s += sq ? ((v0 * v0 + v1 * v1) + (v2 * v2 + v3 * v3)) : ((v0 + v1) + (v2 + v3));
+    nb += (double)(!isfinite(a0)) + (double)(!isfinite(a1)) + (double)(!isfinite(a2)) + (double)(!isfinite(a3));
+  }
+  for (; m < N; m += B) {
+    const double v = a[m] - shiftv;
+    s += sq ? v * v : v;
+    if (!isfinite(a[m])) nb += 1.0;
+  }
+  double v2[2] = {s, nb};
+  const int op[2] = {0, 0};
+  block_reduce<2>(v2, op, sh);
+  sum = v2[0];
+  bad = v2[1];
+}
+
+// Sum, sum of squares and NaN count of a per-chain array in one pass.
+__device__ __forceinline__ void chain_sums2(const double *a, int64_t N, double &sum, double &sq, double &bad,
+                                            double *sh) {
+  double s = 0.0, q = 0.0, nb = 0.0;
+  const int64_t B = blockDim.x;
+  int64_t m = threadIdx.x;
+  for (; m + 3 * B < N; m += 4 * B) {
+    const double a0 = a[m], a1 = a[m + B], a2 = a[m + 2 * B], a3 = a[m + 3 * B];
+    s += (a0 + a1) + (a2 + a3);
+    q += (a0 * a0 + a1 * a1) + (a2 * a2 + a3 * a3);
+    nb += (double)(!isfinite(a0)) + (double)(!isfinite(a1)) + (double)(!isfinite(a2)) + (double)(!isfinite(a3));
+  }
+  for (; m < N; m += B) {
+    const double v = a[m];
+    s += v;
+    q += v * v;
+    if (!isfinite(v)) nb += 1.0;
+  }
+  double v3[3] = {s, q, nb};
+  const int op[3] = {0, 0, 0};
+  block_reduce<3>(v3, op, sh);
+  sum = v3[0];
+  sq = v3[1];
+  bad = v3[2];
+}
+
+// The unadjusted-phase controller (one workgroup of 1024 threads, after the
+// statistics pass of the step has written its block scalars).
+__device__ void ctl_unadj_body(const CtlArgs &c, double *sh, double &mean_sh) {
+  DevHyper *H = c.hyp;
+  double sum, bad, sq;
+  if (c.eevpd_mode == 1) {
+    // mean square: one pass
+    chain_sums2(c.delta, c.N, sum, sq, bad, sh);
+  } else {
+    // variance: two passes about the mean
+    chain_sums(c.delta, c.N, 0.0, 0, sum, bad, sh);
+    if (threadIdx.x == 0) mean_sh = sum / (double)c.N;
+    __syncthreads();
+    double bad2;
+    chain_sums(c.delta, c.N, mean_sh, 1, sq, bad2, sh);
+  }
+  // block scalars of the statistics pass, reduced in a fixed tree order
+  double p3[3] = {0.0, 0.0, -INFINITY};
+  for (int b = threadIdx.x; b < c.nb; b += blockDim.x) {
+    p3[0] += c.part2[b * 4 + 0];
+    p3[1] += c.part2[b * 4 + 1];
+    p3[2] = nanmax(p3[2], c.part2[b * 4 + 2]);
+  }
+  const int op3[3] = {0, 0, 1};
+  block_reduce<3>(p3, op3, sh);
+  if (threadIdx.x != 0) return;
+  const double sD = p3[0], sV = p3[1], mx = p3[2];
+  H->dtilde = sD / (double)c.d;
+  H->eevpd = sq / (double)c.N / (double)c.d;
+  H->n_nonfinite = (int64_t)bad;
+  if (bad > 0.0) H->status |= ST_NONFINITE;
+  H->eevpd_target = F_bias(c.C * H->dtilde);
+  const double ratio = H->eevpd_target / H->eevpd;
+  if (isfinite(ratio) && ratio > 0.0)
+    H->eps *= pow(ratio, 1.0 / 6.0);
+  else
+    H->status |= ST_EPS_KEPT;
+  H->sum_var = sV;
+  H->L = c.alpha * sqrt(sV);
+  H->ring_pos = (H->ring_pos + 1) % c.Tw;
+  if (H->ring_count < c.Tw) H->ring_count += 1;
+  if (H->ring_count == c.Tw) {
+    H->max_delta = mx;
+    H->switch_ready = (mx < c.switch_tol) ? 1 : 0;
+  } else {
+    H->max_delta = INFINITY;
+    H->switch_ready = 0;
+  }
+  H->t += 1;
+  H->grads += 1;
+  if ((c.switch_policy == 0 && H->switch_ready) || H->t >= c.max_unadj) H->phase = PH_SWITCH_PENDING;
+}
+
 // 32 dimensions per 1024-thread block: lane group rg (0..31) of dimension
 // column dl sums partial rows rg, rg + 32, ...; the 32 group sums are then
 // added in group order, so the result does not depend on timing.  The moving
@@ -160,61 +268,6 @@ __global__ void __launch_bounds__(1024) k_finalize(CtlArgs c, int mode) {
   }
 }
 
-__device__ __forceinline__ double F_bias(double D) {
-  const double r = sqrt(D);
-  return 4.0 * D * r / ((1.0 + r) * (1.0 + r));
-}
-
-// Sum (and NaN count) of a per-chain array over one 256-thread block.
-__device__ __forceinline__ void chain_sums(const double *a, int64_t N, double shiftv, int sq, double &sum,
-                                           double &bad, double *sh) {
-  double s = 0.0, nb = 0.0;
-  int64_t m = threadIdx.x;
-  const int64_t B = blockDim.x;
-  for (; m + 3 * B < N; m += 4 * B) {
-    const double a0 = a[m], a1 = a[m + B], a2 = a[m + 2 * B], a3 = a[m + 3 * B];
-    const double v0 = a0 - shiftv, v1 = a1 - shiftv, v2 = a2 - shiftv, v3 = a3 - shiftv;
-    s += sq ? ((v0 * v0 + v1 * v1) + (v2 * v2 + v3 * v3)) : ((v0 + v1) + (v2 + v3));
-    nb += (double)(!isfinite(a0)) + (double)(!isfinite(a1)) + (double)(!isfinite(a2)) + (double)(!isfinite(a3));
-  }
-  for (; m < N; m += B) {
-    const double v = a[m] - shiftv;
-    s += sq ? v * v : v;
-    if (!isfinite(a[m])) nb += 1.0;
-  }
-  double v2[2] = {s, nb};
-  const int op[2] = {0, 0};
-  block_reduce<2>(v2, op, sh);
-  sum = v2[0];
-  bad = v2[1];
-}
-
-// Sum, sum of squares and NaN count of a per-chain array in one pass.
-__device__ __forceinline__ void chain_sums2(const double *a, int64_t N, double &sum, double &sq, double &bad,
-                                            double *sh) {
-  double s = 0.0, q = 0.0, nb = 0.0;
-  const int64_t B = blockDim.x;
-  int64_t m = threadIdx.x;
-  for (; m + 3 * B < N; m += 4 * B) {
-    const double a0 = a[m], a1 = a[m + B], a2 = a[m + 2 * B], a3 = a[m + 3 * B];
-    s += (a0 + a1) + (a2 + a3);
-    q += (a0 * a0 + a1 * a1) + (a2 * a2 + a3 * a3);
-    nb += (double)(!isfinite(a0)) + (double)(!isfinite(a1)) + (double)(!isfinite(a2)) + (double)(!isfinite(a3));
-  }
-  for (; m < N; m += B) {
-    const double v = a[m];
-    s += v;
-    q += v * v;
-    if (!isfinite(v)) nb += 1.0;
-  }
-  double v3[3] = {s, q, nb};
-  const int op[3] = {0, 0, 0};
-  block_reduce<3>(v3, op, sh);
-  sum = v3[0];
-  sq = v3[1];
-  bad = v3[2];
-}
-
 __global__ void __launch_bounds__(256) k_ctl_init(CtlArgs c) {
   __shared__ double sh[4 * 4];
   (void)sh;
@@ -227,57 +280,10 @@ __global__ void __launch_bounds__(256) k_ctl_init(CtlArgs c) {
 }
 
 __global__ void __launch_bounds__(1024) k_ctl_unadj(CtlArgs c) {
-  DevHyper *H = c.hyp;
-  if (H->phase != PH_UNADJ) return;
+  if (c.hyp->phase != PH_UNADJ) return;
   __shared__ double sh[16 * 4];
   __shared__ double mean_sh;
-  double sum, bad, sq;
-  if (c.eevpd_mode == 1) {
-    // mean square: one pass
-    chain_sums2(c.delta, c.N, sum, sq, bad, sh);
-  } else {
-    // variance: two passes about the mean
-    chain_sums(c.delta, c.N, 0.0, 0, sum, bad, sh);
-    if (threadIdx.x == 0) mean_sh = sum / (double)c.N;
-    __syncthreads();
-    double bad2;
-    chain_sums(c.delta, c.N, mean_sh, 1, sq, bad2, sh);
-  }
-  // block scalars of the statistics pass, reduced in a fixed tree order
-  double p3[3] = {0.0, 0.0, -INFINITY};
-  for (int b = threadIdx.x; b < c.nb; b += blockDim.x) {
-    p3[0] += c.part2[b * 4 + 0];
-    p3[1] += c.part2[b * 4 + 1];
-    p3[2] = nanmax(p3[2], c.part2[b * 4 + 2]);
-  }
-  const int op3[3] = {0, 0, 1};
-  block_reduce<3>(p3, op3, sh);
-  if (threadIdx.x != 0) return;
-  const double sD = p3[0], sV = p3[1], mx = p3[2];
-  H->dtilde = sD / (double)c.d;
-  H->eevpd = sq / (double)c.N / (double)c.d;
-  H->n_nonfinite = (int64_t)bad;
-  if (bad > 0.0) H->status |= ST_NONFINITE;
-  H->eevpd_target = F_bias(c.C * H->dtilde);
-  const double ratio = H->eevpd_target / H->eevpd;
-  if (isfinite(ratio) && ratio > 0.0)
-    H->eps *= pow(ratio, 1.0 / 6.0);
-  else
-    H->status |= ST_EPS_KEPT;
-  H->sum_var = sV;
-  H->L = c.alpha * sqrt(sV);
-  H->ring_pos = (H->ring_pos + 1) % c.Tw;
-  if (H->ring_count < c.Tw) H->ring_count += 1;
-  if (H->ring_count == c.Tw) {
-    H->max_delta = mx;
-    H->switch_ready = (mx < c.switch_tol) ? 1 : 0;
-  } else {
-    H->max_delta = INFINITY;
-    H->switch_ready = 0;
-  }
-  H->t += 1;
-  H->grads += 1;
-  if ((c.switch_policy == 0 && H->switch_ready) || H->t >= c.max_unadj) H->phase = PH_SWITCH_PENDING;
+  ctl_unadj_body(c, sh, mean_sh);
 }
 
 // One thread per dimension; block 0 thread 0 also sets the phase block.
@@ -360,16 +366,17 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
+hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_unadj, dim3(1), dim3(1024), 0, s, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const CtlArgs &c, int mode, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(c.nb), dim3(1024), 0, s, c, mode);
   return hipGetLastError();
 }
 hipError_t launch_ctl_init(const CtlArgs &c, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(256), 0, s, c);
-  return hipGetLastError();
-}
-hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_unadj, dim3(1), dim3(1024), 0, s, c);
   return hipGetLastError();
 }
 hipError_t launch_switch(const CtlArgs &c, hipStream_t s) {

@@ -61,9 +61,9 @@ enum { FIN_INIT = 0, FIN_UNADJ = 1 };
 hipError_t launch_hyper_init(const CtlArgs &c, hipStream_t s);
 hipError_t launch_finalize(const CtlArgs &c, int mode, hipStream_t s);
 hipError_t launch_ctl_init(const CtlArgs &c, hipStream_t s);
-hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s);
 hipError_t launch_switch(const CtlArgs &c, hipStream_t s);
 hipError_t launch_ctl_adj(const CtlArgs &c, hipStream_t s);
+hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 
 enum KernelKind { KK_INIT = 0, KK_UNADJ = 1, KK_MAMS_MN2 = 2, KK_MAMS_MN4 = 3, KK_EVAL = 4 };
@@ -77,6 +77,9 @@ hipError_t launch_local_sv(bool dbl, int Q, KernelKind kk, const LocalArgs &a, i
                            hipStream_t s);
 hipError_t launch_local_phi4(bool dbl, int Q, KernelKind kk, const LocalArgs &a, int grid, int block, size_t shmem,
                              hipStream_t s);
+// Raises a kernel's dynamic LDS limit to at least `bytes` (no-op up to 64 KiB;
+// gfx950 gives a workgroup up to 160 KiB).  Grants are remembered per kernel.
+hipError_t grant_lds(const void *kernel, size_t bytes);
 hipError_t launch_prep_aux(int kind, bool dbl, const void *src, void *aux, int64_t d, int64_t ld, hipStream_t s);
 // Per-dimension ensemble sums of (x - K, (x - K)^2, (x - K) g, g) over CB
 // chain blocks, one partial row per block (used when the step kernel does not
@@ -106,6 +109,10 @@ struct LogregArgs {
   double Lp_factor;
   int gate;                // 0: always; 1: unadjusted phase; 2: adjusted phase below max_total
   int mode, j, k, integ;   // update-kernel selector
+  // integrator coefficients of the stage (set by the host per launch): b_0,
+  // a_0, b_{k+1}, a_{k+1} and the stage count K
+  double cb0, ca0, cbk, cak;
+  int cK;
 };
 
 enum { LR_INIT = 0, LR_PRE = 1, LR_POST = 2, LR_MBEGIN = 3, LR_MSTEP = 4 };

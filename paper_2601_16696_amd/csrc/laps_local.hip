@@ -2,9 +2,24 @@
 // they rely on: the column sums of the per-dimension ensemble statistics and
 // the per-dimension target constants.  The per-chain kernels themselves are
 // instantiated per target in laps_local_{gauss,sv,phi4}.hip.
+#include <mutex>
+#include <unordered_map>
+
 #include "laps_team.hpp"
 
 namespace laps {
+
+hipError_t grant_lds(const void *kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  static std::mutex mu;
+  static std::unordered_map<const void *, size_t> granted;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t &have = granted[kernel];
+  if (bytes <= have) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) have = bytes;
+  return e;
+}
 
 // Column sums over a block of chains: thread i of grid column cb owns
 // dimension i and walks chains cb, cb + CB, ... in order (coalesced across the

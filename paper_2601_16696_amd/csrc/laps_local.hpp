@@ -792,30 +792,28 @@ __global__ void __launch_bounds__(512) k_eval(LocalArgs a) {
 // ---------------------------------------------------------------------------
 template <class Real, int Q, class Tgt>
 hipError_t launch_kind(KernelKind kk, const LocalArgs &a, int grid, int block, size_t shmem, hipStream_t s) {
+  void (*fn)(LocalArgs) = nullptr;
   switch (kk) {
     case KK_INIT:
-      if constexpr (Q == 1) {
-        if (a.stats) {
-          hipLaunchKernelGGL((k_init<Real, Q, Tgt, true>), dim3(grid), dim3(block), shmem, s, a);
-          break;
-        }
-      }
-      hipLaunchKernelGGL((k_init<Real, Q, Tgt, false>), dim3(grid), dim3(block), shmem, s, a);
+      fn = k_init<Real, Q, Tgt, false>;
+      if constexpr (Q == 1)
+        if (a.stats) fn = k_init<Real, Q, Tgt, true>;
       break;
     case KK_UNADJ:
-      if constexpr (Q == 1) {
-        if (a.stats) {
-          hipLaunchKernelGGL((k_unadj<Real, Q, Tgt, true>), dim3(grid), dim3(block), shmem, s, a);
-          break;
-        }
-      }
-      hipLaunchKernelGGL((k_unadj<Real, Q, Tgt, false>), dim3(grid), dim3(block), shmem, s, a);
+      fn = k_unadj<Real, Q, Tgt, false>;
+      if constexpr (Q == 1)
+        if (a.stats) fn = k_unadj<Real, Q, Tgt, true>;
       break;
-    case KK_MAMS_MN2: hipLaunchKernelGGL((k_mams<Real, Q, Tgt, 1>), dim3(grid), dim3(block), shmem, s, a); break;
-    case KK_MAMS_MN4: hipLaunchKernelGGL((k_mams<Real, Q, Tgt, 2>), dim3(grid), dim3(block), shmem, s, a); break;
-    case KK_EVAL: hipLaunchKernelGGL((k_eval<Real, Q, Tgt>), dim3(grid), dim3(block), shmem, s, a); break;
+    case KK_MAMS_MN2: fn = k_mams<Real, Q, Tgt, 1>; break;
+    case KK_MAMS_MN4: fn = k_mams<Real, Q, Tgt, 2>; break;
+    case KK_EVAL: fn = k_eval<Real, Q, Tgt>; break;
   }
-  return hipGetLastError();
+  if (!fn) return hipErrorInvalidValue;
+  const hipError_t e = grant_lds(reinterpret_cast<const void *>(fn), shmem);
+  if (e != hipSuccess) return e;
+  LocalArgs arg = a;
+  void *args[] = {&arg};
+  return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(block), args, shmem, s);
 }
 
 // Octs per lane that have kernel instances: 1..6 for FP32 state, 1..2 for

@@ -28,12 +28,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-// The eight-wavefront staged gradient kernel is the default; LAPS_LR_KERNEL=pipe
-// selects the pipelined one (d <= 128).
-bool lr_pipelined() {
+// The direct-to-LDS gradient kernel is the default for d <= 128;
+// LAPS_LR_KERNEL=staged selects the register-staged one.
+static bool lr_lds_kernel() {
   static const int v = [] {
     const char *e = getenv("LAPS_LR_KERNEL");
-    return (e && e[0] == 'p') ? 1 : 0;
+    return (e && e[0] == 's') ? 0 : 1;
   }();
   return v != 0;
 }
@@ -41,8 +41,9 @@ bool lr_pipelined() {
 void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int &S, int &NB, int &bps) {
   NB = (int)((n + 31) / 32);
   const int64_t groups = (N + 63) / 64;
-  // workgroups of one gradient launch: two per CU for the pipelined bf16 kernel, one otherwise
-  int64_t target = (prec != 0 && d <= 128 && lr_pipelined()) ? 512 : 256;
+  // workgroups of one gradient launch: two per CU for the direct-to-LDS bf16
+  // kernel (which two workgroups per CU fit), one per CU otherwise
+  int64_t target = (prec != 0 && d <= 128 && lr_lds_kernel()) ? 512 : 256;
   if (const char *e = getenv("LAPS_LR_WGS")) target = atol(e) > 0 ? atol(e) : target;
   int64_t want = target / (groups > 0 ? groups : 1);
   if (want < 1) want = 1;
@@ -274,22 +275,41 @@ __global__ void __launch_bounds__(512) k_lr_grad_bf16(LogregArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// bf16 matrix-core gradient, pipelined (d <= 128).  grid (ceil(N/64), S),
-// 256 threads = 4 wavefronts; wavefront w owns chain group w (16 chains) and
-// walks every 32-row block of the split.  The blocks' operand fragments and
-// labels pass through a three-stage LDS ring shared by the four chain groups:
-// at block i a wavefront reads stage i (backward fragments, labels) and stage
-// i + 1 (forward fragments), while the workgroup stages block i + 2.  The
-// forward products of block i + 1 are issued before the epilogue of block i,
-// so the matrix cores work while the vector ALU evaluates the sigmoid and
-// softplus terms.  One barrier per block; two workgroups share a CU.
+// bf16 matrix-core gradient with direct-to-LDS staging (d <= 128).  The work
+// split is the staged kernel's (grid (ceil(N/64), S), 8 wavefronts: chain
+// group w % 4, row half w / 4), but the operand fragments of the next two
+// blocks go from global memory straight into LDS (global_load_lds_dwordx4:
+// one wavefront instruction writes 64 consecutive 16-byte fragments), so no
+// registers carry them; fragments are read from LDS where they are used, and
+// theta's hi and lo products accumulate into one register tile.  The kernel
+// keeps to 128 VGPRs, so two workgroups (16 wavefronts) share a CU and one
+// workgroup's matrix-core phase overlaps the other's vector epilogue.
 // ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void lds_dma16(const bf16x8 *src, bf16x8 *lds_dst) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_dst, 16, 0, 0);
+}
+
 template <int KC, bool FULL>
-__device__ __forceinline__ void lr_epilogue(const f32x4 (&z)[2], const float *Y, int q, int nvalid, bf16x8 &rb,
-                                            double &lacc) {
+__device__ __forceinline__ void lr_block_lean(const bf16x8 *L, const float *Y, int lane, int q, int nvalid,
+                                              const bf16x8 (&thi)[KC], const bf16x8 (&tlo)[KC],
+                                              f32x4 (&gacc)[2 * KC], double &lacc) {
+  f32x4 z[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bf16x8 af = L[(h * KC + kc) * 64 + lane];
+      z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, thi[kc], z[h], 0, 0, 0);
+      z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, tlo[kc], z[h], 0, 0, 0);
+    }
   const float4 y0 = *reinterpret_cast<const float4 *>(Y + 4 * q);
   const float4 y1 = *reinterpret_cast<const float4 *>(Y + 16 + 4 * q);
   const float yv[2][4] = {{y0.x, y0.y, y0.z, y0.w}, {y1.x, y1.y, y1.z, y1.w}};
+  // r = y - sigmoid(z); log p terms y z - softplus(z), the lane's eight
+  // log(1 + e^{-|z|}) taken as one log of their product (factors in (1, 2])
+  bf16x8 rb;
   float lin = 0.f, prod = 1.f;
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -297,48 +317,67 @@ __device__ __forceinline__ void lr_epilogue(const f32x4 (&z)[2], const float *Y,
     for (int i = 0; i < 4; ++i) {
       const float zz = z[h][i];
       const bool ok = FULL || (16 * h + 4 * q + i < nvalid);
-      const float e = __expf(-fabsf(zz));
+      const float e = ok ? __expf(-fabsf(zz)) : 0.f;
       const float ope = 1.0f + e;
       const float inv = __builtin_amdgcn_rcpf(ope);
       const float sig = zz >= 0.f ? inv : e * inv;
       rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - sig : 0.f);
       lin += ok ? yv[h][i] * zz - fmaxf(zz, 0.f) : 0.f;
-      prod *= ok ? ope : 1.0f;
+      prod *= ope;
     }
   lacc += (double)lin - (double)__logf(prod);
-}
-
-template <int KC>
-__device__ __forceinline__ void lr_forward(const bf16x8 *L, int lane, const bf16x8 (&thi)[KC],
-                                           const bf16x8 (&tlo)[KC], f32x4 (&z)[2]) {
-  z[0] = f32x4{0.f, 0.f, 0.f, 0.f};
-  z[1] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kc = 0; kc < KC; ++kc) {
-    const bf16x8 a0 = L[kc * 64 + lane], a1 = L[(KC + kc) * 64 + lane];
-    z[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, thi[kc], z[0], 0, 0, 0);
-    z[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, thi[kc], z[1], 0, 0, 0);
-    z[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, tlo[kc], z[0], 0, 0, 0);
-    z[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, tlo[kc], z[1], 0, 0, 0);
+  for (int dc = 0; dc < 2 * KC; ++dc) {
+    const bf16x8 bfr = L[2 * KC * 64 + dc * 64 + lane];
+    gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr, rb, gacc[dc], 0, 0, 0);
   }
 }
 
 template <int KC>
-__global__ void __launch_bounds__(256) k_lr_grad_bf16_pipe(LogregArgs a) {
+__global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
   if (!lr_gate(a)) return;
-  constexpr int kF = 2 * KC * 64;          // forward (or backward) fragments of one 32-row block
-  constexpr int kStage = 2 * kF + 8;       // + 32 labels (8 x 16 bytes)
-  constexpr int NS = 3;
-  constexpr int kPer = (kStage + 255) / 256;
-  extern __shared__ bf16x8 lds[];          // [NS][kStage]
+  constexpr int kFrag = 4 * KC * 64;      // 16-byte fragments per 32-row block
+  constexpr int kPer = 2 * kFrag / 512;    // fragments per thread per iteration
+  constexpr int kBuf = 2 * kFrag + 16;     // one buffer: two blocks' fragments + their 2 x 32 labels
+  extern __shared__ bf16x8 lds[];          // [2 buffers][kBuf]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  const int cg = wave & 3, rh = wave >> 2;
   const int q = lane >> 4, cl = lane & 15;
   const int64_t N = a.N, ld = a.ld, n = a.n;
-  const int64_t m = ((int64_t)blockIdx.x * 4 + wave) * 16 + cl;
+  const int64_t m = ((int64_t)blockIdx.x * 4 + cg) * 16 + cl;
   const bool mval = m < N;
   const float *X = static_cast<const float *>(a.x);
-  // theta as the B operand: k slot 8q + j of chunk kc is coordinate 32kc + 16(j/4) + 4q + j%4
+  const LrOffsets off = logreg_layout(1, n, a.d, N, ld, a.S);
+  const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
+  const bf16x8 *XB = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xb);
+  const bf16x8 *YF = reinterpret_cast<const bf16x8 *>(a.scratch + off.yf);  // labels, 4 floats per 16 bytes
+  const int s = blockIdx.y;
+  const int b0 = s * a.bps;
+  const int b1 = (b0 + a.bps < a.NB) ? b0 + a.bps : a.NB;
+  const int nit = (b1 - b0 + 1) / 2;
+  // Iteration it stages blocks b0 + 2 it (half 0) and b0 + 2 it + 1 (half 1).
+  // Fragment c of a buffer belongs to half c / kFrag; inside a block the
+  // forward fragments (2 KC x 64) precede the backward ones.  A wavefront's 64
+  // fragments of one instruction lie in one block, so the block test is
+  // uniform per wavefront; lanes 0..15 of wavefront 0 also stage the labels.
+  auto stage = [&](int it, int buf) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int c = tid + 512 * k;
+      const int half = c / kFrag, f = c - half * kFrag;
+      const int64_t blk = b0 + 2 * it + half;
+      if (blk < b1) {
+        const bf16x8 *src = f < 2 * KC * 64 ? XF + blk * 2 * KC * 64 + f : XB + blk * 2 * KC * 64 + (f - 2 * KC * 64);
+        lds_dma16(src, lds + buf * kBuf + (c - lane));
+      }
+    }
+    if (tid < 16) {
+      const int64_t blk = b0 + 2 * it + (tid >> 3);
+      if (blk < b1) lds_dma16(YF + blk * 8 + (tid & 7), lds + buf * kBuf + 2 * kFrag);
+    }
+  };
+  stage(0, 0);
   bf16x8 thi[KC], tlo[KC];
 #pragma unroll
   for (int kc = 0; kc < KC; ++kc) {
@@ -360,77 +399,53 @@ __global__ void __launch_bounds__(256) k_lr_grad_bf16_pipe(LogregArgs a) {
 #pragma unroll
   for (int dc = 0; dc < 2 * KC; ++dc) gacc[dc] = f32x4{0.f, 0.f, 0.f, 0.f};
   double lacc = 0.0;
-  const LrOffsets off = logreg_layout(1, n, a.d, N, ld, a.S);
-  const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
-  const bf16x8 *XB = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xb);
-  const bf16x8 *YF = reinterpret_cast<const bf16x8 *>(a.scratch + off.yf);
-  const int s = blockIdx.y;
-  const int b0 = s * a.bps;
-  const int b1 = (b0 + a.bps < a.NB) ? b0 + a.bps : a.NB;
-  const int nb = b1 - b0;
-  // stage c of block b0 + i: forward fragments, then backward fragments, then labels
-  auto fetch = [&](int i, bf16x8 (&reg)[kPer]) {
-    const int64_t blk = b0 + i;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int c = tid + 256 * k;
-      if (c < kF)
-        reg[k] = XF[blk * kF + c];
-      else if (c < 2 * kF)
-        reg[k] = XB[blk * kF + (c - kF)];
-      else if (c < kStage)
-        reg[k] = YF[blk * 8 + (c - 2 * kF)];
-    }
-  };
-  auto stash = [&](int i, const bf16x8 (&reg)[kPer]) {
-    bf16x8 *S = lds + (i % NS) * kStage;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int c = tid + 256 * k;
-      if (c < kStage) S[c] = reg[k];
-    }
-  };
-  bf16x8 reg[kPer];
-  for (int i = 0; i < NS - 1 && i < nb; ++i) {
-    fetch(i, reg);
-    stash(i, reg);
-  }
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  f32x4 zc[2], zn[2];
-  if (nb > 0) lr_forward<KC>(lds, lane, thi, tlo, zc);
-  for (int i = 0; i < nb; ++i) {
-    const bool pre = i + NS - 1 < nb;
-    if (pre) fetch(i + NS - 1, reg);
-    const bf16x8 *Lc = lds + (i % NS) * kStage;
-    if (i + 1 < nb) lr_forward<KC>(lds + ((i + 1) % NS) * kStage, lane, thi, tlo, zn);
-    bf16x8 rb;
-    const float *Y = reinterpret_cast<const float *>(Lc + 2 * kF);
-    const int64_t nv = n - 32 * (int64_t)(b0 + i);
-    if (nv >= 32)
-      lr_epilogue<KC, true>(zc, Y, q, 32, rb, lacc);
-    else
-      lr_epilogue<KC, false>(zc, Y, q, (int)nv, rb, lacc);
-#pragma unroll
-    for (int dc = 0; dc < 2 * KC; ++dc)
-      gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Lc[kF + dc * 64 + lane], rb, gacc[dc], 0, 0, 0);
-    zc[0] = zn[0];
-    zc[1] = zn[1];
-    if (pre) stash(i + NS - 1, reg);
+  for (int it = 0; it < nit; ++it) {
+    // the other buffer was last read in iteration it - 1, which ended in a barrier
+    if (it + 1 < nit) stage(it + 1, (it + 1) & 1);
+    const int64_t blk = b0 + 2 * it + rh;
+    if (blk < b1) {
+      const bf16x8 *L = lds + (it & 1) * kBuf + rh * kFrag;
+      const float *Y = reinterpret_cast<const float *>(lds + (it & 1) * kBuf + 2 * kFrag + 8 * rh);
+      const int64_t nv = n - 32 * blk;
+      if (nv >= 32)
+        lr_block_lean<KC, true>(L, Y, lane, q, 32, thi, tlo, gacc, lacc);
+      else
+        lr_block_lean<KC, false>(L, Y, lane, q, (int)nv, thi, tlo, gacc, lacc);
+    }
+    // this thread's fragments of iteration it + 1 are in LDS; the barrier
+    // publishes everyone's and retires the reads of the current buffer
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
-  float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
-  if (mval) {
+  // half 1 hands its partial sums to half 0 through LDS (fixed order: half 0 + half 1)
+  float *red = reinterpret_cast<float *>(lds);
+  double *lred = reinterpret_cast<double *>(red + 4 * 64 * 8 * KC);
+  if (rh == 1) {
 #pragma unroll
     for (int dc = 0; dc < 2 * KC; ++dc)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t dd = 16 * dc + 4 * q + i;
-        if (dd < ld) Gp[dd] = gacc[dc][i];
-      }
+      for (int i = 0; i < 4; ++i) red[((cg * 2 * KC + dc) * 4 + i) * 64 + lane] = gacc[dc][i];
+    lred[cg * 64 + lane] = lacc;
   }
-  lacc += __shfl_xor(lacc, 16);
-  lacc += __shfl_xor(lacc, 32);
-  if (mval && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
+  __syncthreads();
+  if (rh == 0) {
+    float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
+    if (mval) {
+#pragma unroll
+      for (int dc = 0; dc < 2 * KC; ++dc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t dd = 16 * dc + 4 * q + i;
+          if (dd < ld) Gp[dd] = gacc[dc][i] + red[((cg * 2 * KC + dc) * 4 + i) * 64 + lane];
+        }
+    }
+    lacc += lred[cg * 64 + lane];
+    lacc += __shfl_xor(lacc, 16);
+    lacc += __shfl_xor(lacc, 32);
+    if (mval && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -625,19 +640,39 @@ __device__ __forceinline__ void lr_grad_sum(const LogregArgs &a, const LrOffsets
   const double *lp = reinterpret_cast<const double *>(a.scratch + off.lp);
   const int64_t e0 = 8 * (int64_t)r;
   Real acc[8] = {};
-  if (act && e0 < a.d) {
-    for (int s = 0; s < a.S; ++s) {
-      Real v[8];
+  lps = 0.0;
+  // splits in order, four at a time: the four loads are issued before the
+  // first of them is used, so the split sum costs ~S/4 memory latencies
+  const int S = act ? a.S : 0;
+  const bool mine = e0 < a.d;
+  int s = 0;
+  for (; s + 4 <= S; s += 4) {
+    Real v[4][8];
+    double l[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (mine) ld8<Real>(Gp + ((int64_t)(s + k) * a.N + m) * a.ld + e0, v[k]);
+      l[k] = lp[(int64_t)(s + k) * a.N + m];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (mine)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] += v[k][i];
+      lps += l[k];
+    }
+  }
+  for (; s < S; ++s) {
+    Real v[8];
+    if (mine) {
       ld8<Real>(Gp + ((int64_t)s * a.N + m) * a.ld + e0, v);
 #pragma unroll
       for (int i = 0; i < 8; ++i) acc[i] += v[i];
     }
+    lps += lp[(int64_t)s * a.N + m];
   }
 #pragma unroll
   for (int i = 0; i < 8; ++i) g[0][i] = (e0 + i < a.d) ? acc[i] - x[0][i] : Real(0);
-  lps = 0.0;
-  if (act)
-    for (int s = 0; s < a.S; ++s) lps += lp[(int64_t)s * a.N + m];
 }
 
 template <class Real>
@@ -785,7 +820,6 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   }
 
   // adjusted phase: preconditioned MAMS trajectory, one stage per launch
-  const Coeffs C = integrator_coeffs(a.integ);
   const double Lp = a.Lp_factor * (double)a.n_traj * eps;
   const Real c1 = (Real)exp(-h / Lp), c2 = (Real)(sqrt(-expm1(-2.0 * h / Lp)) / sqrt((double)d));
   Real sg[1][8];
@@ -807,9 +841,9 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     }
     team_sum<3>(v, T, red, slot);
     const double inw = 1.0 / sqrt(v[0]);
-    const BMap b = b_map_t<Real>(v[2], v[1] * inw, C.b[0] * eps, dm1);
+    const BMap b = b_map_t<Real>(v[2], v[1] * inw, a.cb0 * eps, dm1);
     D += b.dK;
-    const Real Ab = (Real)(b.A * inw), Bb = (Real)b.Bg, ha = (Real)(C.a[0] * eps);
+    const Real Ab = (Real)(b.A * inw), Bb = (Real)b.Bg, ha = (Real)(a.ca0 * eps);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       u[0][i] = Ab * u[0][i] + Bb * sg[0][i] * g[0][i];
@@ -863,14 +897,14 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   lprev = lnew;
   const int k = a.k, j = a.j;
   {
-    const BMap b = b_map_t<Real>(v[1], v[2], C.b[k + 1] * eps, dm1);
+    const BMap b = b_map_t<Real>(v[1], v[2], a.cbk * eps, dm1);
     D += b.dK;
     const Real Ab = (Real)b.A, Bb = (Real)b.Bg;
 #pragma unroll
     for (int i = 0; i < 8; ++i) u[0][i] = Ab * u[0][i] + Bb * sg[0][i] * g[0][i];
   }
-  if (k + 1 < C.K - 1) {
-    const Real ha = (Real)(C.a[k + 1] * eps);
+  if (k + 1 < a.cK - 1) {
+    const Real ha = (Real)(a.cak * eps);
 #pragma unroll
     for (int i = 0; i < 8; ++i) x[0][i] += ha * sg[0][i] * u[0][i];
   } else {
@@ -962,17 +996,18 @@ hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
     return hipGetLastError();
   }
   const dim3 grid((unsigned)((a.N + 63) / 64), (unsigned)a.S);
-  if (a.KC <= 4 && lr_pipelined()) {
-    const size_t shp = (size_t)3 * (4 * a.KC * 64 + 8) * 16;
-    switch (a.KC) {
-      case 1: hipLaunchKernelGGL(k_lr_grad_bf16_pipe<1>, grid, dim3(256), shp, s, a); break;
-      case 2: hipLaunchKernelGGL(k_lr_grad_bf16_pipe<2>, grid, dim3(256), shp, s, a); break;
-      case 3: hipLaunchKernelGGL(k_lr_grad_bf16_pipe<3>, grid, dim3(256), shp, s, a); break;
-      case 4: hipLaunchKernelGGL(k_lr_grad_bf16_pipe<4>, grid, dim3(256), shp, s, a); break;
-    }
-    return hipGetLastError();
-  }
   const size_t shm = (size_t)2 * (2 * 4 * a.KC * 64 + 16) * 16;
+  if (a.KC <= 4 && lr_lds_kernel()) {
+    void (*fn)(LogregArgs) = a.KC == 1 ? k_lr_grad_bf16_lds<1>
+                             : a.KC == 2 ? k_lr_grad_bf16_lds<2>
+                             : a.KC == 3 ? k_lr_grad_bf16_lds<3>
+                                         : k_lr_grad_bf16_lds<4>;
+    const hipError_t e = grant_lds(reinterpret_cast<const void *>(fn), shm);
+    if (e != hipSuccess) return e;
+    LogregArgs arg = a;
+    void *args[] = {&arg};
+    return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, dim3(512), args, shm, s);
+  }
   switch (a.KC) {
     case 1: return launch_staged<1>(grid, shm, a, s);
     case 2: return launch_staged<2>(grid, shm, a, s);

@@ -56,7 +56,8 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["laps_config_default", "laps_row_stride", "laps_workspace_size", "laps_init", "laps_step_unadjusted",
            "laps_step_adjusted", "laps_ensemble_stats", "laps_target_eval", "laps_philox_words",
-           "laps_philox_normals", "laps_time_gradient", "laps_time_kernel", "laps_restart", "laps_graph_create",
+           "laps_philox_normals", "laps_time_gradient", "laps_time_kernel", "laps_kernel_log",
+           "laps_kernel_log_read", "laps_restart", "laps_graph_create",
            "laps_graph_launch", "laps_graph_destroy", "laps_buffer", "laps_destroy", "laps_status_string",
            "laps_last_error"]
 
@@ -87,6 +88,8 @@ def lib():
         "laps_philox_normals": (I32, [U64, I64, I64, U64, U32, U32, I32, P, P]),
         "laps_time_gradient": (I32, [P, I32, P]),
         "laps_time_kernel": (I32, [P, I32, I32, P]),
+        "laps_kernel_log": (I32, [P, I32, I32, I32]),
+        "laps_kernel_log_read": (I32, [P, P, P]),
         "laps_restart": (I32, [P, P]),
         "laps_graph_create": (I32, [P, I32, I32, P, I64, I64, P]),
         "laps_graph_launch": (I32, [P, P]),
@@ -259,6 +262,22 @@ class Sampler:
         ms = ctypes.c_float(0.0)
         _check(lib().laps_time_kernel(self.ctx, {"unadj": 1, "adj": 2}[which], n_reps, ctypes.byref(ms)), self.ctx)
         return ms.value
+
+    KERNELS = {"unadj": 1, "adj": 2, "grad": 3}
+
+    def kernel_log(self, which: str, capacity: int, every: int = 1):
+        """Records HIP events around every `every`-th launch of one kernel of
+        the following steps, up to `capacity` launches ("unadj" / "adj":
+        per-chain step kernels, "grad": the logistic-regression gradient
+        kernel); capacity 0 stops."""
+        _check(lib().laps_kernel_log(self.ctx, self.KERNELS[which] if capacity else 0, capacity, every), self.ctx)
+
+    def kernel_log_read(self):
+        """(launches logged, summed milliseconds) of the kernel log."""
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check(lib().laps_kernel_log_read(self.ctx, ctypes.byref(n), ctypes.byref(ms)), self.ctx)
+        return n.value, ms.value
 
     def time_gradient(self, n_reps: int = 20) -> float:
         """Mean milliseconds of one ensemble gradient evaluation (HIP events on the sampler's stream)."""

@@ -82,3 +82,40 @@ def test_segment_graphs_replay_eager_runs(gpu):
             _ = s.stats()
         torch.cuda.synchronize()
         assert torch.isfinite(junk)
+
+
+@pytest.mark.parametrize("spec", [("gauss", "unadj"), ("logreg", "grad")])
+def test_kernel_log_counts_launches(gpu, spec):
+    """The event log brackets every launch of the chosen kernel inside the
+    steps that follow (one per unadjusted step; for logistic regression also
+    the MAMS trajectory's gradients), leaves the run's results unchanged, and
+    graph recording refuses a logging context."""
+    import torch
+    name, which = spec
+    w = workloads.gaussian(n_chains=64, d=30) if name == "gauss" else workloads.logreg(n_chains=64, n=200, d=20)
+    prec = "f64" if name == "gauss" else "bf16"
+    cfg = dict(switch_policy=1, max_steps_unadj=10, max_steps_total=10 + 15 * 2, integrator_adj=1)
+    ref = gpu.Sampler(w, prec, **cfg)
+    _run(ref, 10, 1)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s = gpu.Sampler(w, prec, **cfg)
+    s.kernel_log(which, 100)
+    with pytest.raises(gpu.LapsError):
+        gpu.RunGraph([s], 1, 0)
+    _run(s, 10, 1)
+    n, ms = s.kernel_log_read()
+    # MN2 takes two gradients per integrator step of the 15-step trajectory
+    assert n == (10 if which == "unadj" else 10 + 2 * 15)
+    assert ms > 0.0
+    s.kernel_log(which, 0)
+    assert s.kernel_log_read() == (0, 0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(s.x, ref.x)
+    # one launch in three: the first, the fourth, ...
+    s.restart(torch.as_tensor(w["x0"], device="cuda:0").to(s.x.dtype))
+    s.kernel_log(which, 100, 3)
+    _run(s, 10, 1)
+    n3, _ = s.kernel_log_read()
+    assert n3 == (n + 2) // 3
+    s.kernel_log(which, 0)
