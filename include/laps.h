@@ -77,8 +77,26 @@ typedef enum { LAPS_F64 = 0, LAPS_F32 = 1, LAPS_MIXED_BF16 = 2 } laps_precision;
  *                    + m2/2 phi_x^2 + lambda phi_x^4].
  *                                                dims[0] = L, scal[0] = m2,
  *                                                scal[1] = lambda
+ *   LAPS_CALLBACK    a caller-supplied log p (the method's general input: any
+ *                    differentiable log density).  cb and cb_user below.
  * Target data must stay valid and unchanged while a context uses it. */
-typedef enum { LAPS_GAUSS_DIAG = 0, LAPS_LOGREG = 1, LAPS_STOCHVOL = 2, LAPS_PHI4 = 3 } laps_target_kind;
+typedef enum { LAPS_GAUSS_DIAG = 0, LAPS_LOGREG = 1, LAPS_STOCHVOL = 2, LAPS_PHI4 = 3, LAPS_CALLBACK = 4 } laps_target_kind;
+
+/* Gradient callback of a LAPS_CALLBACK target.  The library calls it on the
+ * host thread that enqueues a step, each time the ensemble needs log p and its
+ * gradient (once per unadjusted step, once per gradient stage of a MAMS
+ * trajectory, once at initialisation).  It must enqueue on `stream` (a
+ * hipStream_t) device work that reads the positions x_dev [n_chains][ld] and
+ * writes, for every chain m and coordinate i < d, g_dev[m*ld + i] =
+ * d log p(x_m) / d x_i and logp_dev[m] = log p(x_m) (double); columns d..ld-1
+ * of g_dev are ignored.  x_dev and g_dev hold the state type (double for
+ * LAPS_F64, float for LAPS_F32) and are device buffers of the library's
+ * workspace, valid only until the enqueued work completes.  It must not
+ * synchronise the device or free memory, and returns 0 on success (non-zero
+ * fails the step with LAPS_EDEVICE).  Work it enqueues is captured with the
+ * steps by laps_graph_create if it is capturable. */
+typedef int (*laps_grad_cb)(void *user, const void *x_dev, void *g_dev, double *logp_dev, int64_t n_chains,
+                            int64_t d, int64_t ld, void *stream);
 
 typedef struct {
   int32_t kind; /* laps_target_kind */
@@ -86,6 +104,8 @@ typedef struct {
   const void *data[4];
   int64_t dims[4];
   double scal[4];
+  laps_grad_cb cb; /* LAPS_CALLBACK only */
+  void *cb_user;   /* passed to cb unchanged */
 } laps_target;
 
 /* Sampler configuration.  Zero-initialise and call laps_config_default() to

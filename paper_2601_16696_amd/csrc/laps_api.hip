@@ -156,9 +156,10 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape
 bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
   const bool dbl = cfg->prec == LAPS_F64;
   if (is_local(tg->kind)) return local_shape(tg->kind, dbl, cfg->n_chains, cfg->d, cfg->team_lanes, s);
-  if (tg->kind == LAPS_LOGREG) {
+  if (tg->kind == LAPS_LOGREG || tg->kind == LAPS_CALLBACK) {
+    // per-chain update kernels: one oct per lane, up to 64 lanes
     const int64_t octs = (cfg->d + 7) / 8;
-    if (cfg->d > 320) return false;
+    if (cfg->d > (tg->kind == LAPS_LOGREG ? 320 : 512)) return false;
     int T = 1;
     while (T < octs) T <<= 1;
     s.T = T;
@@ -220,6 +221,9 @@ Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
     int S, NB, bps;
     logreg_splits(tg->dims[0], N, cfg->prec, d, S, NB, bps);
     lr = logreg_layout(cfg->prec == LAPS_F64 ? 0 : 1, tg->dims[0], d, N, ld, S).total;
+  } else if (tg->kind == LAPS_CALLBACK) {
+    // one partial-sum "split": the callback's g and log p
+    lr = logreg_layout(cfg->prec == LAPS_F64 ? 0 : 1, 0, d, N, ld, 1).total;
   }
   L.packed = c.take(lr);
   L.total = (size_t)round_up((int64_t)c.off, 256);
@@ -263,6 +267,16 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
       // cause shown yet; it is refused until one is.  d <= 200 selects MN2 automatically.
       if (integ_for(cfg) == 2)
         return why = "logistic regression with the MN4 integrator (d > 200 or integrator_adj = 2) is disabled",
+               LAPS_EUNSUPPORTED;
+      break;
+    case LAPS_CALLBACK:
+      if (!tg->cb) return why = "a callback target needs cb", LAPS_EINVAL;
+      if (cfg->prec == LAPS_MIXED_BF16) return why = "a callback target runs in LAPS_F64 or LAPS_F32", LAPS_EUNSUPPORTED;
+      if (cfg->d > 512) return why = "a callback target supports d <= 512", LAPS_EUNSUPPORTED;
+      // same update kernels as logistic regression, so the same MN4 restriction
+      if (integ_for(cfg) == 2)
+        return why = "a callback target with the MN4 integrator (d > 200 or integrator_adj = 2) is disabled; set "
+                     "integrator_adj = 1",
                LAPS_EUNSUPPORTED;
       break;
     default:
@@ -325,7 +339,16 @@ LogregArgs logreg_args(laps_ctx *c, int gate) {
   a.N = c->cfg.n_chains;
   a.d = c->cfg.d;
   a.ld = c->ld;
-  logreg_splits(a.n, a.N, c->cfg.prec, a.d, a.S, a.NB, a.bps);
+  if (c->tg.kind == LAPS_CALLBACK) {
+    a.n = 0;
+    a.S = 1;
+    a.NB = 0;
+    a.bps = 0;
+    a.prior = 0;
+  } else {
+    logreg_splits(a.n, a.N, c->cfg.prec, a.d, a.S, a.NB, a.bps);
+    a.prior = 1;
+  }
   a.KC = (int)((a.d + 31) / 32);
   a.T = c->T;
   a.tpw = c->tpw;
@@ -432,18 +455,29 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     a.cak = k + 1 < 5 ? C.a[k + 1] : 0.0;
     return launch_logreg_update(prec, a, c->G, c->shmem, c->stream);
   };
+  const bool cb = c->tg.kind == LAPS_CALLBACK;
+  int cb_rc = 0;
+  // the ensemble gradient: the logistic-regression kernels, or the caller's
+  // callback writing the single partial-sum split
+  auto grad = [&](const LogregArgs &a) -> hipError_t {
+    if (!cb) return launch_logreg_grad(prec, a, c->stream);
+    const LrOffsets off = logreg_layout(c->dbl ? 0 : 1, 0, a.d, a.N, a.ld, 1);
+    cb_rc = c->tg.cb(c->tg.cb_user, c->x, a.scratch + off.Gp, reinterpret_cast<double *>(a.scratch + off.lp), a.N,
+                     a.d, a.ld, c->stream);
+    return cb_rc == 0 ? hipSuccess : hipErrorUnknown;
+  };
   hipError_t e = hipSuccess;
   if (kk == KK_INIT) {
     LogregArgs a = logreg_args(c, 0);
     a.u0 = u0;
-    if (prec != LAPS_F64 && !c->packed_ok) e = launch_logreg_pack(a, c->stream);
+    if (!cb && prec != LAPS_F64 && !c->packed_ok) e = launch_logreg_pack(a, c->stream);
     if (e == hipSuccess) c->packed_ok = true;
-    if (e == hipSuccess) e = launch_logreg_grad(prec, a, c->stream);
+    if (e == hipSuccess) e = grad(a);
     if (e == hipSuccess) e = upd(a, LR_INIT, 0, 0);
   } else if (kk == KK_UNADJ) {
     LogregArgs a = logreg_args(c, 1);
     e = upd(a, LR_PRE, 0, 0);
-    if (e == hipSuccess) e = logged(c, LAPS_KERNEL_GRAD, [&] { return launch_logreg_grad(prec, a, c->stream); });
+    if (e == hipSuccess) e = logged(c, LAPS_KERNEL_GRAD, [&] { return grad(a); });
     if (e == hipSuccess) e = upd(a, LR_POST, 0, 0);
   } else {
     LogregArgs a = logreg_args(c, 2);
@@ -451,11 +485,16 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     e = upd(a, LR_MBEGIN, 0, 0);
     for (int j = 0; j < c->cfg.n_steps_traj && e == hipSuccess; ++j)
       for (int k = 0; k < K - 1 && e == hipSuccess; ++k) {
-        e = logged(c, LAPS_KERNEL_GRAD, [&] { return launch_logreg_grad(prec, a, c->stream); });
+        e = logged(c, LAPS_KERNEL_GRAD, [&] { return grad(a); });
         if (e == hipSuccess) e = upd(a, LR_MSTEP, j, k);
       }
   }
-  return e == hipSuccess ? LAPS_OK : fail(c, e, "logistic-regression kernels");
+  if (e == hipSuccess) return LAPS_OK;
+  if (cb_rc != 0) {
+    c->err = g_last_global = "gradient callback returned " + std::to_string(cb_rc);
+    return LAPS_EDEVICE;
+  }
+  return fail(c, e, cb ? "update kernels" : "logistic-regression kernels");
 }
 
 }  // namespace
@@ -920,6 +959,12 @@ extern "C" laps_status laps_time_gradient(laps_ctx *c, int32_t n_reps, float *av
       a.logp_out = c->logp;
       a.g_out = c->g;
       e = launch_local(c->tg.kind, c->dbl, c->Q, KK_EVAL, a, c->grid_full, c->block, c->shmem, c->stream);
+    } else if (c->tg.kind == LAPS_CALLBACK) {
+      LogregArgs a = logreg_args(c, 0);
+      const LrOffsets off = logreg_layout(c->dbl ? 0 : 1, 0, a.d, a.N, a.ld, 1);
+      if (c->tg.cb(c->tg.cb_user, c->x, a.scratch + off.Gp, reinterpret_cast<double *>(a.scratch + off.lp), a.N,
+                   a.d, a.ld, c->stream) != 0)
+        e = hipErrorUnknown;
     } else {
       LogregArgs a = logreg_args(c, 0);
       e = launch_logreg_grad(c->cfg.prec, a, c->stream);

@@ -113,6 +113,7 @@ struct LogregArgs {
   // a_0, b_{k+1}, a_{k+1} and the stage count K
   double cb0, ca0, cbk, cak;
   int cK;
+  int prior;               // 1: add the N(0, I) prior of logistic regression to the partial sums; 0: caller's log p
 };
 
 enum { LR_INIT = 0, LR_PRE = 1, LR_POST = 2, LR_MBEGIN = 3, LR_MSTEP = 4 };

@@ -18,6 +18,10 @@
 //
 // Plain FP64 (LAPS_F64): the same partial-sum interface with a double-precision
 // vector-ALU gradient (the baseline the mixed path is measured against).
+//
+// The per-chain update kernels also serve caller-supplied targets: the
+// caller's gradient callback writes one "split" of partial sums (g and log p
+// without the prior), and the kernels run unchanged with prior = 0.
 #include <stdlib.h>
 
 #include "laps_team.hpp"
@@ -672,7 +676,7 @@ __device__ __forceinline__ void lr_grad_sum(const LogregArgs &a, const LrOffsets
     lps += lp[(int64_t)s * a.N + m];
   }
 #pragma unroll
-  for (int i = 0; i < 8; ++i) g[0][i] = (e0 + i < a.d) ? acc[i] - x[0][i] : Real(0);
+  for (int i = 0; i < 8; ++i) g[0][i] = (e0 + i < a.d) ? acc[i] - (a.prior ? x[0][i] : Real(0)) : Real(0);
 }
 
 template <class Real>
@@ -723,7 +727,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
         v[2] += (double)z[0][i] * (double)z[0][i];
       }
       team_sum<3>(v, T, red, slot);
-      const double l1 = lps - 0.5 * v[0];
+      const double l1 = lps - (a.prior ? 0.5 * v[0] : 0.0);
       if (a.u0) {
         load_row<Real, 1>(static_cast<const Real *>(a.u0) + m * ld, r, T, d, act, u);
       } else {
@@ -756,7 +760,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
         v[2] += (double)g[0][i] * (double)u[0][i];
       }
       team_sum<3>(v, T, red, slot);
-      const double l1 = lps - 0.5 * v[0];
+      const double l1 = lps - (a.prior ? 0.5 * v[0] : 0.0);
       const BMap b2 = b_map_t<Real>(v[1], v[2], h, dm1);
       lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, 0, z);
       double w1[1] = {0.0};
@@ -892,7 +896,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     v[2] += (double)gt * (double)u[0][i];
   }
   team_sum<3>(v, T, red, slot);
-  const double lnew = lps - 0.5 * v[0];
+  const double lnew = lps - (a.prior ? 0.5 * v[0] : 0.0);
   D = (act ? sc_D[m] + (sc_lprev[m] - lnew) : 0.0);
   lprev = lnew;
   const int k = a.k, j = a.j;

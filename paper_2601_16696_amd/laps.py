@@ -16,9 +16,12 @@ LIB_PATH = os.path.join(_HERE, "liblaps_hip.so")
 
 OK, EINVAL, EDEVICE, ENONFINITE, EPHASE, EWORKSPACE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 F64, F32, MIXED_BF16 = 0, 1, 2
-GAUSS_DIAG, LOGREG, STOCHVOL, PHI4 = 0, 1, 2, 3
+GAUSS_DIAG, LOGREG, STOCHVOL, PHI4, CALLBACK = 0, 1, 2, 3, 4
 PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, F64: F64, F32: F32, MIXED_BF16: MIXED_BF16}
-KINDS = {"gauss": GAUSS_DIAG, "logreg": LOGREG, "stochvol": STOCHVOL, "phi4": PHI4}
+KINDS = {"gauss": GAUSS_DIAG, "logreg": LOGREG, "stochvol": STOCHVOL, "phi4": PHI4, "callback": CALLBACK}
+# laps_grad_cb: (user, x_dev, g_dev, logp_dev, n_chains, d, ld, stream) -> int
+GRAD_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p)
 
 
 class LapsError(RuntimeError):
@@ -40,7 +43,8 @@ class Config(ctypes.Structure):
 
 class TargetS(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("d", ctypes.c_int64), ("data", ctypes.c_void_p * 4),
-                ("dims", ctypes.c_int64 * 4), ("scal", ctypes.c_double * 4)]
+                ("dims", ctypes.c_int64 * 4), ("scal", ctypes.c_double * 4), ("cb", ctypes.c_void_p),
+                ("cb_user", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -175,7 +179,46 @@ class Target:
             s.data[0] = tX.data_ptr()
             s.data[1] = ty.data_ptr()
             s.dims[0] = int(X.shape[0])
+        elif self.kind == CALLBACK:
+            self._set_callback(w["fn"])
+            s.cb = ctypes.cast(self._cb, ctypes.c_void_p)
         self.s = s
+
+    def _set_callback(self, fn):
+        """fn(x, g, logp) is called with torch views of the library's buffers
+        (x, g: [N, ld] in the state type; logp: [N] float64) on the stream the
+        library names, and must write g[:, :d] = grad log p(x) and logp.  The
+        views alias device memory registered in self.buffers (the sampler's
+        positions and workspace)."""
+        import traceback
+        self.buffers = []
+
+        def view(ptr, shape, dtype):
+            torch = _torch()
+            nbytes = int(np.prod(shape)) * torch.empty((), dtype=dtype).element_size()
+            for t in self.buffers:
+                base = t.data_ptr()
+                size = t.numel() * t.element_size()
+                if base <= ptr and ptr + nbytes <= base + size:
+                    off = ptr - base
+                    return t.reshape(-1).view(torch.uint8)[off:off + nbytes].view(dtype).view(shape)
+            raise RuntimeError("callback pointer outside the registered buffers")
+
+        def tramp(user, xp, gp, lpp, n, d, ld, stream):
+            try:
+                torch = _torch()
+                dt = _state_dtype(self.prec)
+                x, g = view(xp, (n, ld), dt), view(gp, (n, ld), dt)
+                lp = view(lpp, (n,), torch.float64)
+                st = torch.cuda.ExternalStream(stream) if stream else torch.cuda.default_stream()
+                with torch.cuda.stream(st):
+                    fn(x, g, lp)
+                return 0
+            except Exception:
+                traceback.print_exc()
+                return 1
+
+        self._cb = GRAD_CB(tramp)
 
     def eval(self, x, grad: bool = True, stream=None):
         """log p [n] (float64) and gradient [n, d] for rows of x ([n, d] or padded [n, ld])."""
@@ -231,6 +274,8 @@ class Sampler:
         _check(lib().laps_workspace_size(ctypes.byref(c), ctypes.byref(self.target.s), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        if self.target.kind == CALLBACK:
+            self.target.buffers += [self.x, self.ws]
         self.per_dim = torch.empty((4, d), dtype=torch.float64, device=device)
         self.ctx = ctypes.c_void_p()
         self._init()

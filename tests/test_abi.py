@@ -151,3 +151,26 @@ def test_logreg_mn4_refused(L):
     c, t = _cfg_target(L, kind=1, d=100)
     c.integrator_adj = 2
     assert _ws(L, c, t)[0] == L.EUNSUPPORTED
+
+
+def test_callback_target_validation(L):
+    """A caller-supplied target needs a callback, runs in FP64 or FP32 state,
+    supports d <= 512 (one oct per lane, 64 lanes) and, like logistic
+    regression, only the MN2 adjusted integrator."""
+    c, t = _cfg_target(L, kind=L.CALLBACK, d=30)
+    assert _ws(L, c, t)[0] == L.EINVAL            # no callback
+    t.cb = 0x3000
+    assert _ws(L, c, t)[0] == L.OK
+    c.prec = L.F32
+    assert _ws(L, c, t)[0] == L.OK
+    c.prec = L.MIXED_BF16
+    assert _ws(L, c, t)[0] == L.EUNSUPPORTED
+    c, t = _cfg_target(L, kind=L.CALLBACK, d=300)
+    t.cb = 0x3000
+    assert _ws(L, c, t)[0] == L.EUNSUPPORTED      # d > 200 selects MN4
+    c.integrator_adj = 1
+    assert _ws(L, c, t)[0] == L.OK
+    c, t = _cfg_target(L, kind=L.CALLBACK, d=513)
+    t.cb = 0x3000
+    c.integrator_adj = 1
+    assert _ws(L, c, t)[0] == L.EUNSUPPORTED
