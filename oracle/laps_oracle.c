@@ -84,6 +84,17 @@ double orc_mh_uniform(uint64_t seed, uint64_t chain, uint64_t t) {
   return orc_u01(w[0]);
 }
 
+void orc_rademacher(uint64_t seed, uint64_t t, int64_t p, int64_t d, double *z) {
+  const uint64_t key[2] = {seed, 0};
+  for (int64_t i = 0; i < d; ++i) {
+    uint64_t ctr[4] = {(uint64_t)p, (uint64_t)(i / 256), t, (uint64_t)ORC_TAG_PROBE}, w[4];
+    orc_philox4x64_10(ctr, key, w);
+    const int64_t b = i % 256;
+    const uint64_t bit = (w[b / 64] >> (b % 64)) & 1u;
+    z[i] = bit ? -1.0 : 1.0;
+  }
+}
+
 /* ======================================================================
  * Compensated summation (Neumaier 1974) in the given order.
  * ==================================================================== */
@@ -343,6 +354,40 @@ double orc_F(double D) {
   return 4.0 * D * r / ((1.0 + r) * (1.0 + r));
 }
 
+/* Full-rank equipartition loss (section "Equipartition condition", full-rank
+ * paragraph; Hutchinson 1989): V_ij = -E[(x_i - E x_i) g_j] (eq. for the
+ * equipartition matrix, ensemble averages of eq. ECA) gives
+ * (I - V) z = z + (1/N) sum_m (x_m - xbar)(g_m . z), and the loss (1/d)
+ * Tr((I - V)(I - V)^T) is estimated as the mean of |(I - V) z|^2 / d over the
+ * probes.  Plain loops; ensemble sums compensated, in chain order. */
+double orc_dtilde_full(const double *x, const double *g, int64_t N, int64_t d, const double *z, int64_t P) {
+  double *xbar = (double *)calloc((size_t)d, sizeof(double));
+  double *s = (double *)calloc((size_t)N, sizeof(double));
+  for (int64_t i = 0; i < d; ++i) {
+    nsum a = {0, 0};
+    for (int64_t m = 0; m < N; ++m) nsum_add(&a, x[m * d + i]);
+    xbar[i] = nsum_get(&a) / (double)N;
+  }
+  nsum tot = {0, 0};
+  for (int64_t p = 0; p < P; ++p) {
+    const double *zp = z + p * d;
+    for (int64_t m = 0; m < N; ++m) {  /* s_m = g_m . z_p */
+      nsum a = {0, 0};
+      for (int64_t i = 0; i < d; ++i) nsum_add(&a, g[m * d + i] * zp[i]);
+      s[m] = nsum_get(&a);
+    }
+    for (int64_t i = 0; i < d; ++i) {
+      nsum a = {0, 0};
+      for (int64_t m = 0; m < N; ++m) nsum_add(&a, (x[m * d + i] - xbar[i]) * s[m]);
+      const double w = zp[i] + nsum_get(&a) / (double)N;
+      nsum_add(&tot, w * w);
+    }
+  }
+  free(xbar);
+  free(s);
+  return nsum_get(&tot) / ((double)P * (double)d);
+}
+
 /* Per-dim ensemble moments of the current x and g (eq. ECA, 1/M averages,
  * R8): mean, two-pass variance, second moment and the equipartition
  * diagonal V_ii = -E[(x_i - E x_i) d_i log p]. */
@@ -458,8 +503,14 @@ void orc_unadj_control(orc_ctx *c) {
   if (c->phase != PH_UNADJ) return;
   const int64_t N = c->N, d = c->d;
   ensemble_moments(c);
-  /* equipartition loss, diagonal form */
-  {
+  /* equipartition loss, diagonal form, or full rank from fresh probes of this step */
+  if (c->cfg.full_rank_probes > 0) {
+    const int64_t P = c->cfg.full_rank_probes;
+    double *z = (double *)calloc((size_t)(P * d), sizeof(double));
+    for (int64_t p = 0; p < P; ++p) orc_rademacher(c->cfg.seed, (uint64_t)c->t, p, d, z + p * d);
+    c->dtilde = orc_dtilde_full(c->x, c->g, N, d, z, P);
+    free(z);
+  } else {
     nsum s = {0, 0};
     for (int64_t i = 0; i < d; ++i) nsum_add(&s, (1.0 - c->Vii[i]) * (1.0 - c->Vii[i]));
     c->dtilde = nsum_get(&s) / (double)d;

@@ -24,7 +24,7 @@ extern "C" {
 
 /* ---- counter-based random numbers (Philox4x64-10, Salmon et al. SC'11) ---- */
 enum { ORC_TAG_O_FIRST = 1, ORC_TAG_O_SECOND = 2, ORC_TAG_FULL_REFRESH = 3,
-       ORC_TAG_MH = 4, ORC_TAG_INIT_DIR = 5 };
+       ORC_TAG_MH = 4, ORC_TAG_INIT_DIR = 5, ORC_TAG_PROBE = 6 };
 
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 double orc_u01(uint64_t w);
@@ -32,6 +32,9 @@ double orc_u01(uint64_t w);
 void orc_normals(uint64_t seed, uint64_t chain, uint64_t t, uint32_t tag,
                  uint32_t substep, int64_t d, double *z);
 double orc_mh_uniform(uint64_t seed, uint64_t chain, uint64_t t);
+/* Rademacher probe p of step t (entries +-1): entry i is 1 - 2 b, where b is
+ * bit i mod 64 of word (i mod 256) / 64 of Philox block (p, i / 256, t, 6). */
+void orc_rademacher(uint64_t seed, uint64_t t, int64_t p, int64_t d, double *z);
 
 /* ---- targets (log p up to an additive constant, and its gradient) ---- */
 enum { ORC_GAUSS_DIAG = 0, ORC_LOGREG = 1, ORC_STOCHVOL = 2, ORC_PHI4 = 3 };
@@ -61,9 +64,17 @@ typedef struct {
   double C, alpha, eps0_factor, switch_tol, window_frac, acc_tol, acc_target, L_partial_factor;
   int32_t n_steps_traj, integrator_adj, eevpd_mode, switch_policy;
   int64_t max_steps_unadj, max_steps_total;
+  int32_t full_rank_probes; /* 0: diagonal equipartition loss; P > 0: full rank, P Rademacher probes */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;
+
+/* Full-rank equipartition loss by Hutchinson's trace estimator (section
+ * "Equipartition condition", full-rank paragraph): for positions x and
+ * gradients g of N chains ([N][d]) and P probes z ([P][d]),
+ *   (1/(P d)) sum_p |z_p + (1/N) sum_m (x_m - xbar)(g_m . z_p)|^2,
+ * the mean over probes of |(I - V) z|^2 / d with V from ensemble averages. */
+double orc_dtilde_full(const double *x, const double *g, int64_t N, int64_t d, const double *z, int64_t P);
 
 orc_ctx *orc_create(const orc_config *cfg, const orc_target *tg);
 void orc_destroy(orc_ctx *c);

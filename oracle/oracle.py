@@ -45,7 +45,7 @@ class _Config(ctypes.Structure):
                 ("L_partial_factor", ctypes.c_double), ("n_steps_traj", ctypes.c_int32),
                 ("integrator_adj", ctypes.c_int32), ("eevpd_mode", ctypes.c_int32),
                 ("switch_policy", ctypes.c_int32), ("max_steps_unadj", ctypes.c_int64),
-                ("max_steps_total", ctypes.c_int64)]
+                ("max_steps_total", ctypes.c_int64), ("full_rank_probes", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -94,6 +94,8 @@ def lib():
             "orc_set_hyper": (None, [P, D, D]),
             "orc_F": (D, [D]),
             "orc_sum": (D, [P, I64]),
+            "orc_rademacher": (None, [U64, U64, I64, I64, P]),
+            "orc_dtilde_full": (D, [P, P, I64, I64, P, I64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -131,6 +133,21 @@ def normals(seed, chain, t, tag, substep, d) -> np.ndarray:
 
 def mh_uniform(seed, chain, t) -> float:
     return lib().orc_mh_uniform(seed, chain, t)
+
+
+def rademacher(seed, t, p, d) -> np.ndarray:
+    """Probe p of step t: entries +-1 from the bits of Philox blocks (p, i // 256, t, 6)."""
+    z = np.zeros(d)
+    lib().orc_rademacher(seed, t, p, d, _p(z))
+    return z
+
+
+def dtilde_full(x, g, z) -> float:
+    """Hutchinson estimate of the full-rank equipartition loss for positions x,
+    gradients g ([N, d]) and probes z ([P, d])."""
+    x, g, z = _f64(x), _f64(g), _f64(z)
+    N, d = x.shape
+    return lib().orc_dtilde_full(_p(x), _p(g), N, d, _p(z), z.shape[0])
 
 
 # ----------------------------------------------------------------------------- targets
@@ -213,7 +230,7 @@ def fsum(v) -> float:
 # ----------------------------------------------------------------------------- ensemble
 DEFAULTS = dict(C=0.025, alpha=2.0, eps0_factor=0.01, switch_tol=0.01, window_frac=0.2, acc_tol=0.03,
                 acc_target=0.0, L_partial_factor=1.25, n_steps_traj=15, integrator_adj=0, eevpd_mode=1,
-                switch_policy=0, max_steps_unadj=1000, max_steps_total=2000)
+                switch_policy=0, max_steps_unadj=1000, max_steps_total=2000, full_rank_probes=0)
 
 _ARR = dict(x=0, u=1, g=2, logp=3, delta=4, acc=5, mean=6, var=7, m2=8, Vii=9, sigma=10, ring=11, wdelta=12)
 
@@ -228,7 +245,7 @@ class Ensemble:
         self._c = _Config(n_chains, target.d, seed, c["C"], c["alpha"], c["eps0_factor"], c["switch_tol"],
                           c["window_frac"], c["acc_tol"], c["acc_target"], c["L_partial_factor"],
                           c["n_steps_traj"], c["integrator_adj"], c["eevpd_mode"], c["switch_policy"],
-                          c["max_steps_unadj"], c["max_steps_total"])
+                          c["max_steps_unadj"], c["max_steps_total"], c["full_rank_probes"])
         self.h = lib().orc_create(ctypes.byref(self._c), ctypes.byref(target.s))
         if not self.h:
             raise ValueError("orc_create rejected the configuration")
