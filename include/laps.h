@@ -125,7 +125,10 @@ typedef struct {
  *   switch_policy = 0    0: the paper's fluctuation rule (or max_steps_unadj);
  *                        1: switch exactly at max_steps_unadj
  * Step counts t count integrator steps: one per unadjusted step and
- * n_steps_traj per adjusted transition. */
+ * n_steps_traj per adjusted transition.
+ * Full-rank probes (section "Equipartition condition"): probe p of step t has
+ * entry i = 1 - 2b, b = bit (i mod 64) of word (i mod 256) / 64 of the Philox
+ * block with counter (p, i / 256, t, 6). */
 typedef struct {
   int64_t n_chains, d;
   int32_t prec; /* laps_precision */
@@ -136,7 +139,10 @@ typedef struct {
   int32_t team_lanes; /* launch shape of the per-chain kernels (Gaussian, SV, phi4):
                          0 = automatic; otherwise lanes per chain, a power of two
                          up to 64 or a multiple of 64 up to 512 */
-  int32_t reserved0;  /* zero */
+  int32_t full_rank_probes; /* 0: the diagonal equipartition loss D~_diag (the paper's default);
+                               P in 1..1024: the full-rank loss by Hutchinson's estimator with P
+                               Rademacher probes drawn from the Philox stream each unadjusted
+                               step (the paper uses 100) */
 } laps_config;
 
 /* Snapshot of the device-resident hyperparameters and diagnostics.

@@ -34,6 +34,7 @@ struct laps_ctx {
   DevHyper *hyp;
   void *u, *g, *sigma, *aux, *packed;
   double *logp, *delta, *acc, *partials, *shiftK, *mean, *var, *m2, *Vii, *ring, *wdelta, *part2;
+  double *pS, *pW, *pPart;  // full-rank loss scratch
   std::string err;
   // optional event pairs around the launches of one kernel (laps_kernel_log)
   int log_which = 0, log_every = 1;
@@ -189,8 +190,11 @@ struct Carve {
 
 struct Layout {
   size_t hyp, u, g, logp, delta, acc, partials, shiftK, mean, var, m2, Vii, ring, wdelta, part2, sigma, aux, packed,
-      total;
+      pS, pW, pPart, total;
 };
+
+int probe_chunks(int64_t N) { return (int)((N + kProbeChunk - 1) / kProbeChunk); }
+int probe_blocks(int64_t d, int64_t P) { return (int)((d * P + 255) / 256); }
 
 Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
   const int64_t N = cfg->n_chains, d = cfg->d, ld = laps_row_stride(d);
@@ -226,6 +230,10 @@ Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
     lr = logreg_layout(cfg->prec == LAPS_F64 ? 0 : 1, 0, d, N, ld, 1).total;
   }
   L.packed = c.take(lr);
+  const int64_t P = cfg->full_rank_probes;
+  L.pS = c.take((size_t)N * P * 8);
+  L.pW = c.take((size_t)probe_chunks(N) * P * d * 8);
+  L.pPart = c.take((size_t)(P > 0 ? probe_blocks(d, P) : 0) * 8);
   L.total = (size_t)round_up((int64_t)c.off, 256);
   return L;
 }
@@ -247,6 +255,8 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
       !(cfg->L_partial_factor > 0.0))
     return why = "non-positive constant in config", LAPS_EINVAL;
   if (cfg->team_lanes < 0) return why = "team_lanes must be >= 0", LAPS_EINVAL;
+  if (cfg->full_rank_probes < 0 || cfg->full_rank_probes > 1024)
+    return why = "full_rank_probes must be in 0..1024", LAPS_EINVAL;
   if (cfg->integrator_adj < 0 || cfg->integrator_adj > 2 || cfg->eevpd_mode < 0 || cfg->eevpd_mode > 1 ||
       cfg->switch_policy < 0 || cfg->switch_policy > 1)
     return why = "bad enum in config", LAPS_EINVAL;
@@ -395,6 +405,15 @@ CtlArgs ctl_args(laps_ctx *c) {
   a.max_total = c->cfg.max_steps_total;
   a.sigma = c->sigma;
   a.sigma_double = c->dbl ? 1 : 0;
+  a.probes = c->cfg.full_rank_probes;
+  a.NC = probe_chunks(c->cfg.n_chains);
+  a.nbh = a.probes > 0 ? probe_blocks(c->cfg.d, a.probes) : 0;
+  a.seed = c->cfg.seed;
+  a.x = c->x;
+  a.g = c->g;
+  a.pS = c->pS;
+  a.pW = c->pW;
+  a.pPart = c->pPart;
   return a;
 }
 
@@ -429,7 +448,8 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     a.u0 = u0;
     const bool phase_stats = kk == KK_INIT || kk == KK_UNADJ;
     a.stats = (phase_stats && !c->split) ? 1 : 0;
-    a.cache = (phase_stats && c->split) ? 1 : 0;
+    // the full-rank loss reads the step's gradients, so they are kept
+    a.cache = (phase_stats && (c->split || (kk == KK_UNADJ && c->cfg.full_rank_probes > 0))) ? 1 : 0;
     const int grid = (phase_stats && !c->split) ? c->G : c->grid_full;
     const bool mams = kk == KK_MAMS_MN2 || kk == KK_MAMS_MN4;
     const int which = kk == KK_UNADJ ? LAPS_KERNEL_UNADJ : (mams ? LAPS_KERNEL_MAMS : 0);
@@ -578,6 +598,9 @@ extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, 
   c->sigma = w + L.sigma;
   c->aux = w + L.aux;
   c->packed = w + L.packed;
+  c->pS = reinterpret_cast<double *>(w + L.pS);
+  c->pW = reinterpret_cast<double *>(w + L.pW);
+  c->pPart = reinterpret_cast<double *>(w + L.pPart);
   if (c->shmem_sig > 160 * 1024) {
     // a workgroup of gfx950 holds at most 160 KiB of LDS
     delete c;
@@ -621,6 +644,7 @@ extern "C" laps_status laps_step_unadjusted(laps_ctx *c, int64_t n) {
     laps_status st = enqueue_chain_kernel(c, KK_UNADJ, nullptr);
     if (st != LAPS_OK) return st;
     LAPS_CHECK(c, launch_finalize(ca, FIN_UNADJ, c->stream), "finalize");
+    LAPS_CHECK(c, launch_probes(ca, c->stream), "full-rank loss");
     LAPS_CHECK(c, launch_ctl_unadj(ca, c->stream), "controller");
   }
   return LAPS_OK;

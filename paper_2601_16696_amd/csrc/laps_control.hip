@@ -89,60 +89,58 @@ __device__ __forceinline__ void chain_sums(const double *a, int64_t N, double sh
   bad = v2[1];
 }
 
-// Sum, sum of squares and NaN count of a per-chain array in one pass.
-__device__ __forceinline__ void chain_sums2(const double *a, int64_t N, double &sum, double &sq, double &bad,
-                                            double *sh) {
+// The unadjusted-phase controller (one workgroup of 1024 threads, after the
+// statistics pass of the step has written its block scalars).
+__device__ void ctl_unadj_body(const CtlArgs &c, double *sh, double &mean_sh) {
+  DevHyper *H = c.hyp;
+  // The phase, the energy errors and the statistics pass's block scalars are
+  // loaded together, and their sums share one block reduction; the phase is
+  // tested after it (uniformly, so every thread takes the same path).
+  const int phase = H->phase;
   double s = 0.0, q = 0.0, nb = 0.0;
-  const int64_t B = blockDim.x;
+  const int64_t B = blockDim.x, N = c.N;
   int64_t m = threadIdx.x;
   for (; m + 3 * B < N; m += 4 * B) {
-    const double a0 = a[m], a1 = a[m + B], a2 = a[m + 2 * B], a3 = a[m + 3 * B];
+    const double a0 = c.delta[m], a1 = c.delta[m + B], a2 = c.delta[m + 2 * B], a3 = c.delta[m + 3 * B];
     s += (a0 + a1) + (a2 + a3);
     q += (a0 * a0 + a1 * a1) + (a2 * a2 + a3 * a3);
     nb += (double)(!isfinite(a0)) + (double)(!isfinite(a1)) + (double)(!isfinite(a2)) + (double)(!isfinite(a3));
   }
   for (; m < N; m += B) {
-    const double v = a[m];
+    const double v = c.delta[m];
     s += v;
     q += v * v;
     if (!isfinite(v)) nb += 1.0;
   }
-  double v3[3] = {s, q, nb};
-  const int op[3] = {0, 0, 0};
-  block_reduce<3>(v3, op, sh);
-  sum = v3[0];
-  sq = v3[1];
-  bad = v3[2];
-}
-
-// The unadjusted-phase controller (one workgroup of 1024 threads, after the
-// statistics pass of the step has written its block scalars).
-__device__ void ctl_unadj_body(const CtlArgs &c, double *sh, double &mean_sh) {
-  DevHyper *H = c.hyp;
-  double sum, bad, sq;
-  if (c.eevpd_mode == 1) {
-    // mean square: one pass
-    chain_sums2(c.delta, c.N, sum, sq, bad, sh);
-  } else {
-    // variance: two passes about the mean
-    chain_sums(c.delta, c.N, 0.0, 0, sum, bad, sh);
-    if (threadIdx.x == 0) mean_sh = sum / (double)c.N;
-    __syncthreads();
-    double bad2;
-    chain_sums(c.delta, c.N, mean_sh, 1, sq, bad2, sh);
-  }
-  // block scalars of the statistics pass, reduced in a fixed tree order
   double p3[3] = {0.0, 0.0, -INFINITY};
   for (int b = threadIdx.x; b < c.nb; b += blockDim.x) {
     p3[0] += c.part2[b * 4 + 0];
     p3[1] += c.part2[b * 4 + 1];
     p3[2] = nanmax(p3[2], c.part2[b * 4 + 2]);
   }
-  const int op3[3] = {0, 0, 1};
-  block_reduce<3>(p3, op3, sh);
+  double pr = 0.0;  // full-rank loss: the probe blocks' squared norms
+  if (c.probes > 0)
+    for (int b = threadIdx.x; b < c.nbh; b += blockDim.x) pr += c.pPart[b];
+  double v6[7] = {s, q, nb, p3[0], p3[1], p3[2], pr};
+  const int op6[7] = {0, 0, 0, 0, 0, 1, 0};
+  block_reduce<7>(v6, op6, sh);
+  if (phase != PH_UNADJ) return;
+  const double sum = v6[0], bad = v6[2];
+  double sq = v6[1];
+  p3[0] = v6[3];
+  p3[1] = v6[4];
+  p3[2] = v6[5];
+  if (c.eevpd_mode != 1) {
+    // variance: a second pass about the mean
+    if (threadIdx.x == 0) mean_sh = sum / (double)c.N;
+    __syncthreads();
+    double sum2, bad2;
+    chain_sums(c.delta, c.N, mean_sh, 1, sum2, bad2, sh);
+    sq = sum2;
+  }
   if (threadIdx.x != 0) return;
   const double sD = p3[0], sV = p3[1], mx = p3[2];
-  H->dtilde = sD / (double)c.d;
+  H->dtilde = c.probes > 0 ? v6[6] / ((double)c.probes * (double)c.d) : sD / (double)c.d;
   H->eevpd = sq / (double)c.N / (double)c.d;
   H->n_nonfinite = (int64_t)bad;
   if (bad > 0.0) H->status |= ST_NONFINITE;
@@ -239,19 +237,41 @@ __global__ void __launch_bounds__(1024) k_finalize(CtlArgs c, int mode) {
   if (full) {
     __syncthreads();  // the new window entry is visible to the whole block
     // two-pass mean and sample variance over the window slots
+    // the slots are added in order; eight loads are issued before they are used
     double w1[4] = {0.0, 0.0, 0.0, 0.0};
-    if (act)
-      for (int64_t k = rg; k < c.Tw; k += kFinGroups) w1[0] += c.ring[k * ld + i];
+    if (act) {
+      int64_t k = rg;
+      for (; k + 7 * kFinGroups < c.Tw; k += 8 * kFinGroups) {
+        double r[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = c.ring[(k + j * kFinGroups) * ld + i];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w1[0] += r[j];
+      }
+      for (; k < c.Tw; k += kFinGroups) w1[0] += c.ring[k * ld + i];
+    }
     fin_combine(w1, sh, dl, rg);
     if (rg == 0) mu_sh[dl] = w1[0] / (double)c.Tw;
     __syncthreads();
     const double mu = mu_sh[dl];
     double w2[4] = {0.0, 0.0, 0.0, 0.0};
-    if (act)
-      for (int64_t k = rg; k < c.Tw; k += kFinGroups) {
+    if (act) {
+      int64_t k = rg;
+      for (; k + 7 * kFinGroups < c.Tw; k += 8 * kFinGroups) {
+        double r[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = c.ring[(k + j * kFinGroups) * ld + i];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const double e = r[j] - mu;
+          w2[0] += e * e;
+        }
+      }
+      for (; k < c.Tw; k += kFinGroups) {
         const double e = c.ring[k * ld + i] - mu;
         w2[0] += e * e;
       }
+    }
     fin_combine(w2, sh, dl, rg);
     if (rg == 0 && act) {
       wd = sqrt(w2[0] / (double)(c.Tw - 1)) / mu;
@@ -280,8 +300,7 @@ __global__ void __launch_bounds__(256) k_ctl_init(CtlArgs c) {
 }
 
 __global__ void __launch_bounds__(1024) k_ctl_unadj(CtlArgs c) {
-  if (c.hyp->phase != PH_UNADJ) return;
-  __shared__ double sh[16 * 4];
+  __shared__ double sh[16 * 8];
   __shared__ double mean_sh;
   ctl_unadj_body(c, sh, mean_sh);
 }
@@ -366,6 +385,120 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
+// ---------------------------------------------------------------------------
+// Full-rank equipartition loss by Hutchinson's estimator (section
+// "Equipartition condition", full-rank paragraph): with Rademacher probes z_p
+// of this step and V_ij = -E[(x_i - xbar_i) g_j] from ensemble averages,
+//   D~ = (1/(P d)) sum_p |z_p + (1/N) sum_m (x_m - xbar)(g_m . z_p)|^2.
+// Probe entry i of z_p is 1 - 2b, b = bit i mod 64 of word (i mod 256) / 64 of
+// Philox block (p, i / 256, t, TAG_PROBE); probes are regenerated, never stored.
+// Three passes, every sum in a fixed order:
+//   k_probe_dots:    s[m][p] = g_m . z_p            (one thread per (m, p))
+//   k_probe_project: w_c[p][i] = sum over chunk c of (x_mi - xbar_i) s[m][p]
+//   k_probe_norms:   per block, sum of (z_pi + (1/N) sum_c w_c[p][i])^2
+// and the controller adds the block sums in order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t probe_bits(uint64_t seed, int64_t p, int64_t blk, uint64_t t, int word) {
+  uint64_t w[4] = {(uint64_t)p, (uint64_t)blk, t, (uint64_t)TAG_PROBE};
+  philox4x64_10(w, seed, 0);
+  return w[word];
+}
+
+template <class Real>
+__global__ void __launch_bounds__(256) k_probe_dots(CtlArgs c) {
+  const DevHyper *H = c.hyp;
+  if (H->phase != PH_UNADJ) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t P = c.probes;
+  if (idx >= c.N * P) return;
+  const int64_t m = idx / P, p = idx - m * P;
+  const uint64_t t = (uint64_t)H->t;
+  const Real *g = static_cast<const Real *>(c.g) + m * c.ld;
+  double s = 0.0;
+  for (int64_t b0 = 0; b0 < c.d; b0 += 256) {
+    uint64_t w[4] = {(uint64_t)p, (uint64_t)(b0 / 256), t, (uint64_t)TAG_PROBE};
+    philox4x64_10(w, c.seed, 0);
+    const int64_t e = (c.d - b0 < 256) ? c.d - b0 : 256;
+    for (int64_t k = 0; k < e; k += 8) {
+      Real gv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) gv[j] = (k + j < e) ? g[b0 + k + j] : Real(0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t b = k + j;
+        const double v = (double)gv[j];
+        s += ((w[b >> 6] >> (b & 63)) & 1u) ? -v : v;
+      }
+    }
+  }
+  c.pS[m * P + p] = s;
+}
+
+template <class Real>
+__global__ void __launch_bounds__(256) k_probe_project(CtlArgs c) {
+  const DevHyper *H = c.hyp;
+  if (H->phase != PH_UNADJ) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t P = c.probes, d = c.d;
+  if (idx >= d * P) return;
+  const int64_t p = idx / d, i = idx - p * d;
+  const int64_t m0 = (int64_t)blockIdx.y * kProbeChunk;
+  const int64_t m1 = (m0 + kProbeChunk < c.N) ? m0 + kProbeChunk : c.N;
+  const Real *x = static_cast<const Real *>(c.x);
+  const double xb = c.mean[i];
+  double acc = 0.0;
+  int64_t m = m0;
+  for (; m + 4 <= m1; m += 4) {
+    double xv[4], sv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      xv[j] = (double)x[(m + j) * c.ld + i];
+      sv[j] = c.pS[(m + j) * P + p];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc += (xv[j] - xb) * sv[j];
+  }
+  for (; m < m1; ++m) acc += ((double)x[m * c.ld + i] - xb) * c.pS[m * P + p];
+  c.pW[((int64_t)blockIdx.y * P + p) * d + i] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_probe_norms(CtlArgs c) {
+  const DevHyper *H = c.hyp;
+  if (H->phase != PH_UNADJ) return;
+  __shared__ double sh[4 * 1];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t P = c.probes, d = c.d;
+  double v = 0.0;
+  if (idx < d * P) {
+    const int64_t p = idx / d, i = idx - p * d;
+    double w = 0.0;
+    for (int ch = 0; ch < c.NC; ++ch) w += c.pW[((int64_t)ch * P + p) * d + i];
+    const uint64_t word = probe_bits(c.seed, p, i / 256, (uint64_t)H->t, (int)((i & 255) >> 6));
+    const double z = ((word >> (i & 63)) & 1u) ? -1.0 : 1.0;
+    const double r = z + w / (double)c.N;
+    v = r * r;
+  }
+  double v1[1] = {v};
+  const int op[1] = {0};
+  block_reduce<1>(v1, op, sh);
+  if (threadIdx.x == 0) c.pPart[blockIdx.x] = v1[0];
+}
+
+hipError_t launch_probes(const CtlArgs &c, hipStream_t s) {
+  if (c.probes <= 0) return hipSuccess;
+  const int64_t nd = c.N * c.probes, dp = c.d * c.probes;
+  const dim3 g1((unsigned)((nd + 255) / 256)), g2((unsigned)((dp + 255) / 256), (unsigned)c.NC);
+  if (c.sigma_double) {
+    hipLaunchKernelGGL(k_probe_dots<double>, g1, dim3(256), 0, s, c);
+    hipLaunchKernelGGL(k_probe_project<double>, g2, dim3(256), 0, s, c);
+  } else {
+    hipLaunchKernelGGL(k_probe_dots<float>, g1, dim3(256), 0, s, c);
+    hipLaunchKernelGGL(k_probe_project<float>, g2, dim3(256), 0, s, c);
+  }
+  hipLaunchKernelGGL(k_probe_norms, dim3((unsigned)c.nbh), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_unadj, dim3(1), dim3(1024), 0, s, c);
   return hipGetLastError();

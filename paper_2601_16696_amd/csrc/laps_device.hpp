@@ -17,7 +17,7 @@ struct DevHyper {
 };
 
 enum { PH_UNADJ = 0, PH_SWITCH_PENDING = 1, PH_ADJ = 2 };
-enum { TAG_O_FIRST = 1, TAG_O_SECOND = 2, TAG_FULL_REFRESH = 3, TAG_MH = 4, TAG_INIT_DIR = 5 };
+enum { TAG_O_FIRST = 1, TAG_O_SECOND = 2, TAG_FULL_REFRESH = 3, TAG_MH = 4, TAG_INIT_DIR = 5, TAG_PROBE = 6 };
 enum { ST_NONFINITE = 1, ST_EPS_KEPT = 2, ST_SIGMA_FIX = 4 };
 
 // ---------------------------------------------------------------------------

@@ -53,9 +53,17 @@ struct CtlArgs {
   int64_t max_unadj, max_total;
   void *sigma;
   int sigma_double;
+  // full-rank equipartition loss (probes > 0): positions and gradients of the
+  // step, the probe dot products [N][P], per-chunk projections [NC][P][d] and
+  // per-block squared norms [nbh]
+  int probes, NC, nbh;
+  uint64_t seed;
+  const void *x, *g;
+  double *pS, *pW, *pPart;
 };
 
 enum { FIN_INIT = 0, FIN_UNADJ = 1 };
+constexpr int kProbeChunk = 512;  // chains per partial projection of the full-rank loss
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_hyper_init(const CtlArgs &c, hipStream_t s);
@@ -64,6 +72,7 @@ hipError_t launch_ctl_init(const CtlArgs &c, hipStream_t s);
 hipError_t launch_switch(const CtlArgs &c, hipStream_t s);
 hipError_t launch_ctl_adj(const CtlArgs &c, hipStream_t s);
 hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s);
+hipError_t launch_probes(const CtlArgs &c, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 
 enum KernelKind { KK_INIT = 0, KK_UNADJ = 1, KK_MAMS_MN2 = 2, KK_MAMS_MN4 = 3, KK_EVAL = 4 };

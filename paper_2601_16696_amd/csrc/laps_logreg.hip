@@ -67,7 +67,7 @@ __device__ __forceinline__ bool lr_gate(const LogregArgs &a) {
 // operand packing (bf16 paths), once per context
 //   Xf[b][h][kc][lane][j] = X[32b + 16h + lane%16][32kc + 16(j/4) + 4(lane/16) + j%4]
 //   Xb[b][dc][lane][j]    = X[32b + 16(j/4) + 4(lane/16) + j%4][16dc + lane%16]
-//   yf[row]               = y[row] (0 beyond n)
+//   yf[row]               = y[row] - 1/2 (0 beyond n)
 // ---------------------------------------------------------------------------
 __global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, int64_t d, int KC, int NB,
                           unsigned short *Xf, unsigned short *Xb, float *yf) {
@@ -101,7 +101,7 @@ __global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, i
     return;
   }
   const int64_t t3 = t2 - nbk;
-  if (t3 < (int64_t)NB * 32) yf[t3] = t3 < n ? (float)y[t3] : 0.0f;
+  if (t3 < (int64_t)NB * 32) yf[t3] = t3 < n ? (float)(y[t3] - 0.5) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -139,9 +139,10 @@ __device__ __forceinline__ void lr_block(const bf16x8 *L, const float *Y, int la
   const float4 y0 = *reinterpret_cast<const float4 *>(Y + 4 * q);
   const float4 y1 = *reinterpret_cast<const float4 *>(Y + 16 + 4 * q);
   const float yv[2][4] = {{y0.x, y0.y, y0.z, y0.w}, {y1.x, y1.y, y1.z, y1.w}};
-  // epilogue: r = y - sigmoid(z); log p terms y z - softplus(z), where the
-  // eight log(1 + e^{-|z|}) of the lane are taken as one log of their product
-  // (each factor lies in (1, 2])
+  // epilogue (labels packed as ym = y - 1/2, s = 1/(1 + e^{-|z|})):
+  // r = y - sigmoid(z) = ym - copysign(s - 1/2, z); log p terms
+  // y z - softplus(z) = ym z - |z|/2 - log(1 + e^{-|z|}), where the eight logs
+  // of the lane are taken as one log of their product (factors in (1, 2])
   bf16x8 rb;
   float lin = 0.f, prod = 1.f;
 #pragma unroll
@@ -152,10 +153,9 @@ __device__ __forceinline__ void lr_block(const bf16x8 *L, const float *Y, int la
       const bool ok = FULL || (16 * h + 4 * q + i < nvalid);
       const float e = ok ? __expf(-fabsf(zz)) : 0.f;
       const float ope = 1.0f + e;
-      const float inv = __builtin_amdgcn_rcpf(ope);
-      const float sig = zz >= 0.f ? inv : e * inv;
-      rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - sig : 0.f);
-      lin += ok ? yv[h][i] * zz - fmaxf(zz, 0.f) : 0.f;
+      const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
+      rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - copysignf(t, zz) : 0.f);
+      lin += ok ? fmaf(yv[h][i], zz, -0.5f * fabsf(zz)) : 0.f;
       prod *= ope;
     }
   lacc += (double)lin - (double)__logf(prod);
@@ -311,8 +311,10 @@ __device__ __forceinline__ void lr_block_lean(const bf16x8 *L, const float *Y, i
   const float4 y0 = *reinterpret_cast<const float4 *>(Y + 4 * q);
   const float4 y1 = *reinterpret_cast<const float4 *>(Y + 16 + 4 * q);
   const float yv[2][4] = {{y0.x, y0.y, y0.z, y0.w}, {y1.x, y1.y, y1.z, y1.w}};
-  // r = y - sigmoid(z); log p terms y z - softplus(z), the lane's eight
-  // log(1 + e^{-|z|}) taken as one log of their product (factors in (1, 2])
+  // With the packed label ym = y - 1/2 and s = 1/(1 + e^{-|z|}):
+  //   r = y - sigmoid(z) = ym - copysign(s - 1/2, z)   (s - 1/2 is exact),
+  //   y z - softplus(z) = ym z - |z|/2 - log(1 + e^{-|z|}),
+  // the lane's eight logs taken as one log of their product (factors in (1, 2])
   bf16x8 rb;
   float lin = 0.f, prod = 1.f;
 #pragma unroll
@@ -323,10 +325,9 @@ __device__ __forceinline__ void lr_block_lean(const bf16x8 *L, const float *Y, i
       const bool ok = FULL || (16 * h + 4 * q + i < nvalid);
       const float e = ok ? __expf(-fabsf(zz)) : 0.f;
       const float ope = 1.0f + e;
-      const float inv = __builtin_amdgcn_rcpf(ope);
-      const float sig = zz >= 0.f ? inv : e * inv;
-      rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - sig : 0.f);
-      lin += ok ? yv[h][i] * zz - fmaxf(zz, 0.f) : 0.f;
+      const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
+      rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - copysignf(t, zz) : 0.f);
+      lin += ok ? fmaf(yv[h][i], zz, -0.5f * fabsf(zz)) : 0.f;
       prod *= ope;
     }
   lacc += (double)lin - (double)__logf(prod);
@@ -506,7 +507,9 @@ __global__ void __launch_bounds__(256) k_lr_grad_bf16_direct(LogregArgs a) {
         z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, thi[kc], z[h], 0, 0, 0);
         z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, tlo[kc], z[h], 0, 0, 0);
       }
-    // epilogue: r = y - sigmoid(z), log p terms y z - softplus(z)
+    // epilogue (labels packed as ym = y - 1/2): r = y - sigmoid(z) =
+    // ym - copysign(1/(1 + e^{-|z|}) - 1/2, z), log p terms
+    // y z - softplus(z) = ym z - |z|/2 - log(1 + e^{-|z|})
     bf16x8 rb;
     float lsum = 0.f;
 #pragma unroll
@@ -515,15 +518,13 @@ __global__ void __launch_bounds__(256) k_lr_grad_bf16_direct(LogregArgs a) {
       for (int i = 0; i < 4; ++i) {
         const int64_t row = 32 * (int64_t)b + 16 * h + 4 * q + i;
         const float zz = z[h][i];
-        const float yv = yf[row];
+        const float ym = yf[row];
         const float e = __expf(-fabsf(zz));
         const float ope = 1.0f + e;
-        const float inv = __builtin_amdgcn_rcpf(ope);
-        const float sig = zz >= 0.f ? inv : e * inv;
-        const float sp = fmaxf(zz, 0.f) + __logf(ope);
+        const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
         const bool ok = row < n;
-        rb[4 * h + i] = (__bf16)(ok ? yv - sig : 0.f);
-        lsum += ok ? yv * zz - sp : 0.f;
+        rb[4 * h + i] = (__bf16)(ok ? ym - copysignf(t, zz) : 0.f);
+        lsum += ok ? fmaf(ym, zz, -0.5f * fabsf(zz)) - __logf(ope) : 0.f;
       }
     lacc += (double)lsum;
 #pragma unroll

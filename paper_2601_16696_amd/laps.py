@@ -38,7 +38,7 @@ class Config(ctypes.Structure):
                 ("L_partial_factor", ctypes.c_double), ("n_steps_traj", ctypes.c_int32),
                 ("integrator_adj", ctypes.c_int32), ("eevpd_mode", ctypes.c_int32),
                 ("switch_policy", ctypes.c_int32), ("max_steps_unadj", ctypes.c_int64),
-                ("max_steps_total", ctypes.c_int64), ("team_lanes", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("max_steps_total", ctypes.c_int64), ("team_lanes", ctypes.c_int32), ("full_rank_probes", ctypes.c_int32)]
 
 
 class TargetS(ctypes.Structure):

@@ -174,3 +174,16 @@ def test_callback_target_validation(L):
     t.cb = 0x3000
     c.integrator_adj = 1
     assert _ws(L, c, t)[0] == L.EUNSUPPORTED
+
+
+def test_full_rank_probes_validation(L):
+    c, t = _cfg_target(L, kind=0, N=600, d=300)
+    st0, n0 = _ws(L, c, t)
+    assert st0 == L.OK
+    c.full_rank_probes = 100
+    st1, n1 = _ws(L, c, t)
+    # probe dot products [N][P], per-chunk projections [2 chunks][P][d], block sums
+    assert st1 == L.OK and n1 >= n0 + 8 * (600 * 100 + 2 * 100 * 300)
+    for bad in (-1, 1025):
+        c.full_rank_probes = bad
+        assert _ws(L, c, t)[0] == L.EINVAL
