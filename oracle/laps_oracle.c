@@ -209,9 +209,24 @@ static double t_phi4(const orc_target *tg, const double *x, double *g) {
   return -S;
 }
 
+/* Gaussian with a dense precision matrix A (the rotated ill-conditioned
+ * Gaussian of section "Results"): log p = -x^T A x / 2, gradient -A x. */
+static double t_gauss_dense(const orc_target *tg, const double *x, double *g) {
+  const int64_t d = tg->d;
+  double l = 0.0;
+  for (int64_t i = 0; i < d; ++i) {
+    double ax = 0.0;
+    for (int64_t k = 0; k < d; ++k) ax += tg->a[i * d + k] * x[k];
+    l += -0.5 * x[i] * ax;
+    if (g) g[i] = -ax;
+  }
+  return l;
+}
+
 double orc_logp_grad(const orc_target *tg, const double *x, double *g) {
   switch (tg->kind) {
     case ORC_GAUSS_DIAG: return t_gauss(tg, x, g);
+    case ORC_GAUSS_DENSE: return t_gauss_dense(tg, x, g);
     case ORC_LOGREG: return t_logreg(tg, x, g);
     case ORC_STOCHVOL: return t_stochvol(tg, x, g);
     case ORC_PHI4: return t_phi4(tg, x, g);

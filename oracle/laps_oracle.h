@@ -37,11 +37,11 @@ double orc_mh_uniform(uint64_t seed, uint64_t chain, uint64_t t);
 void orc_rademacher(uint64_t seed, uint64_t t, int64_t p, int64_t d, double *z);
 
 /* ---- targets (log p up to an additive constant, and its gradient) ---- */
-enum { ORC_GAUSS_DIAG = 0, ORC_LOGREG = 1, ORC_STOCHVOL = 2, ORC_PHI4 = 3 };
+enum { ORC_GAUSS_DIAG = 0, ORC_LOGREG = 1, ORC_STOCHVOL = 2, ORC_PHI4 = 3, ORC_GAUSS_DENSE = 5 };
 typedef struct {
   int32_t kind;
   int64_t d;
-  const double *a;  /* gauss: sigma^2 [d]; logreg: X [n][d]; stochvol: y [T] */
+  const double *a;  /* gauss: sigma^2 [d]; logreg: X [n][d]; stochvol: y [T]; gauss_dense: precision [d][d] */
   const double *b;  /* logreg: labels [n] in {0,1} */
   int64_t n;        /* logreg: n data rows; stochvol: T; phi4: side L */
   double p0, p1;    /* phi4: m^2, lambda */

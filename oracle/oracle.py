@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "laps_oracle.c")
 LIB = os.path.join(HERE, "liblaps_oracle.so")
 
-GAUSS_DIAG, LOGREG, STOCHVOL, PHI4 = 0, 1, 2, 3
+GAUSS_DIAG, LOGREG, STOCHVOL, PHI4, GAUSS_DENSE = 0, 1, 2, 3, 5
 TAG_O_FIRST, TAG_O_SECOND, TAG_FULL_REFRESH, TAG_MH, TAG_INIT_DIR = 1, 2, 3, 4, 5
 PH_UNADJ, PH_SWITCH_PENDING, PH_ADJ = 0, 1, 2
 
@@ -172,6 +172,8 @@ class Target:
             return Target(STOCHVOL, w["d"], a=w["y"], n=w["y"].shape[0])
         if k == "phi4":
             return Target(PHI4, w["d"], n=w["side"], p0=w["m2"], p1=w["lam"])
+        if k == "gauss_dense":
+            return Target(GAUSS_DENSE, w["d"], a=w["prec"])
         raise ValueError(k)
 
     def logp_grad(self, x) -> tuple[float, np.ndarray]:

@@ -29,6 +29,23 @@ def gaussian(n_chains: int = 1024, d: int = 100, seed_data: int = 1001, seed_x0:
                 name=f"gaussian_diag_d{d}_N{n_chains}")
 
 
+def ill_gaussian(n_chains: int = 1024, d: int = 100, seed_data: int = 1006, seed_x0: int = 2006,
+                 seed_rng: int = 3006, shape: float = 0.5) -> dict:
+    """Randomly rotated ill-conditioned Gaussian (zero mean): covariance eigenvalues ~ Gamma(shape, 1)
+    (condition number ~1e5 at d = 100), orientation Haar-random (QR of a Gaussian matrix with the sign
+    of R's diagonal folded in); start N(0, I).  prec = covariance^-1, cov_diag = diag(covariance)."""
+    rng = np.random.default_rng(seed_data)
+    lam = rng.gamma(shape, 1.0, size=d)
+    q, r = np.linalg.qr(rng.normal(size=(d, d)))
+    q = q * np.sign(np.diag(r))
+    cov = (q * lam) @ q.T
+    prec = (q / lam) @ q.T
+    cov, prec = 0.5 * (cov + cov.T), 0.5 * (prec + prec.T)
+    x0 = np.random.default_rng(seed_x0).normal(size=(n_chains, d))
+    return dict(kind="gauss_dense", d=d, n_chains=n_chains, prec=prec, cov=cov, cov_diag=np.diag(cov).copy(),
+                cond=float(lam.max() / lam.min()), x0=x0, seed=seed_rng, name=f"ill_gaussian_d{d}_N{n_chains}")
+
+
 def logreg(n_chains: int = 4096, n: int = 5000, d: int = 100, seed_data: int = 1002, seed_x0: int = 2002,
            seed_rng: int = 3002) -> dict:
     """Bayesian logistic regression: X ~ N(0,1) rounded to bf16 (those values define the problem),

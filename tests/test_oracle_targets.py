@@ -140,3 +140,30 @@ def test_phi4_rectangular_indexing_is_periodic(orc):
     assert abs(tgt.logp(np.roll(x, 1, axis=0).ravel()) - l0) < 1e-11
     assert abs(tgt.logp(np.roll(x, 1, axis=1).ravel()) - l0) < 1e-11
     assert abs(tgt.logp(x.T.copy().ravel()) - l0) < 1e-11
+
+
+def test_dense_gauss_against_scipy_and_fd(orc):
+    w = workloads.ill_gaussian(n_chains=4, d=20)
+    tgt = orc.Target.from_workload(w)
+    mvn = stats.multivariate_normal(mean=np.zeros(20), cov=w["cov"])
+    x1, x2 = w["x0"][0], w["x0"][1]
+    ref = mvn.logpdf(x1) - mvn.logpdf(x2)
+    assert abs((tgt.logp(x1) - tgt.logp(x2)) - ref) < 1e-8 * max(1, abs(ref))
+    _check_fd(tgt, x1, rtol=1e-6)
+
+
+def test_dense_gauss_with_diagonal_precision_is_the_diagonal_target(orc):
+    rng = np.random.default_rng(4)
+    s2 = 10 ** rng.uniform(-2, 2, size=12)
+    dense = orc.Target(orc.GAUSS_DENSE, 12, a=np.diag(1.0 / s2))
+    diag = orc.Target(orc.GAUSS_DIAG, 12, a=s2)
+    x = rng.normal(size=12)
+    ld, gd = dense.logp_grad(x)
+    l0, g0 = diag.logp_grad(x)
+    assert abs(ld - l0) <= 1e-13 * abs(l0) and np.allclose(gd, g0, rtol=1e-14, atol=0)
+
+
+def test_ill_gaussian_workload_is_ill_conditioned():
+    w = workloads.ill_gaussian()
+    assert 1e4 < w["cond"] < 1e7
+    assert np.allclose(w["prec"] @ w["cov"], np.eye(100), atol=1e-6 * w["cond"])
