@@ -11,8 +11,10 @@ Default workload: Bayesian logistic regression (X 5000 x 100 N(0,1) rounded to
 bf16, weights N(0, 1/d), Bernoulli labels, N(0, I) prior), 4096 chains, bf16
 matrix-core gradient with FP32 state.  Others: --workload gauss (diagonal
 Gaussian d = 100, 1024 chains, FP64), stochvol (T = 2427, 4096 chains, FP32),
-phi4 (64 x 64 lattice, 2048 chains, FP32), batched (16 targets, 46018 chains,
-run concurrently from recorded segment graphs).
+phi4 (64 x 64 lattice, 2048 chains, FP32), ill_gauss (randomly rotated
+ill-conditioned Gaussian d = 100, dense precision on the matrix cores, 1024
+chains, FP64), batched (16 targets, 46018 chains, run concurrently from
+recorded segment graphs).
 
 value = chain-gradient evaluations per second over the timed runs.
 roofline: the dominant kernel, one launch in ten inside the timed runs bracketed
@@ -63,6 +65,7 @@ WORKLOADS = {
     "gauss": ("gaussian", "f64"),
     "stochvol": ("stochvol", "f32"),
     "phi4": ("phi4", "f32"),
+    "ill_gauss": ("ill_gaussian", "f64"),
     "batched": ("batched_mix", "mixed"),
 }
 
@@ -123,6 +126,7 @@ CPU_SAMPLE = {  # about 10 s of single-threaded oracle work on the same workload
     "gauss": dict(n_chains=1024, n_unadj=600, n_adj=4),
     "stochvol": dict(n_chains=512, n_unadj=20, n_adj=1),
     "phi4": dict(n_chains=512, n_unadj=20, n_adj=1),
+    "ill_gauss": dict(n_chains=1024, n_unadj=500, n_adj=4),
 }
 
 
@@ -146,19 +150,21 @@ def cpu_baseline(w, n_chains=256, n_unadj=10, n_adj=1):
 
 
 # --------------------------------------------------------------------------- time to bias
-def time_to_bias(prec, threshold=0.01):
-    """Diagonal Gaussian d = 100, 1024 chains, with the paper's automatic
-    switch: walks the run step by step (untimed) computing
-    b^2_i = (E[x_i^2] - s2_i)^2 / (2 s2_i^2) from the ensemble after every
-    unadjusted step and every transition, finds the first crossing of
-    b^2_max < threshold, then times a fresh identical run truncated there (the
-    run is deterministic for its seed)."""
+def time_to_bias(prec, threshold=0.01, target="gauss"):
+    """A Gaussian with closed-form moments, 1024 chains, d = 100, the paper's
+    automatic switch: the diagonal Gaussian ("gauss") or the rotated
+    ill-conditioned one ("ill").  Walks the run step by step (untimed)
+    computing b^2_i = (E[x_i^2] - s2_i)^2 / (2 s2_i^2), s2_i the target's
+    variance of x_i, from the ensemble after every unadjusted step and every
+    transition, finds the first crossing of b^2_max < threshold, then times a
+    fresh identical run truncated there (the run is deterministic for its
+    seed)."""
     import torch
     from paper_2601_16696_amd import laps, workloads
-    w = workloads.gaussian()
+    w = workloads.gaussian() if target == "gauss" else workloads.ill_gaussian()
     cfg = dict(switch_policy=0, max_steps_unadj=N_UNADJ, max_steps_total=N_UNADJ + 15 * N_ADJ)
     s = laps.Sampler(w, prec, **cfg)
-    s2 = torch.as_tensor(w["sigma2"], device="cuda:0", dtype=torch.float64)
+    s2 = torch.as_tensor(w["sigma2"] if target == "gauss" else w["cov_diag"], device="cuda:0", dtype=torch.float64)
 
     def b2():
         x = s.positions().to(torch.float64)
@@ -353,7 +359,8 @@ def main():
     prec = args.prec or default_prec
     w = getattr(workloads, gen)()
     N, d = w["n_chains"], w["d"]
-    r = gpu_throughput(w, prec, args.steps, args.warmup, log="grad" if args.workload == "logreg" else "unadj")
+    nonlocal_target = args.workload in ("logreg", "ill_gauss")
+    r = gpu_throughput(w, prec, args.steps, args.warmup, log="grad" if nonlocal_target else "unadj")
     kern = r["kernel"]
     if args.workload == "logreg":
         n = w["X"].shape[0]
@@ -369,6 +376,16 @@ def main():
         precision = ("bf16 matrix-core gradient, fp32 state, fp64 energy error and reductions"
                      if prec == "bf16" else "fp64 throughout")
         extra = {"n": n}
+    elif args.workload == "ill_gauss":
+        work = 2.0 * d * d * N  # flops of A x per ensemble gradient
+        peak = 78.6 if prec == "f64" else 157.3  # dense matrix-core FP64 / FP32
+        achieved = work / (kern["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "kernel": f"k_dense_grad<{'double' if prec == 'f64' else 'float'}>",
+                "kernel_ms": kern["ms"], "launches_timed": kern["launches"], "isolated_kernel_ms": r["grad_ms"],
+                "algorithmic_flops_per_launch": work}
+        precision = "fp64 throughout" if prec == "f64" else "fp32 state, fp64 energy error and reductions"
+        extra = {"condition_number": w["cond"]}
     else:
         rs = 8 if prec == "f64" else 4
         unadj_ms, adj_ms = step_kernel_times(w, prec)
@@ -414,6 +431,12 @@ def main():
         line["time_to_bias"] = {"workload": "gaussian_diag_d100_N1024 (closed-form moments), automatic switch",
                                 "criterion": "first step with b2_max < 0.01",
                                 "f64": time_to_bias("f64"), "f32": time_to_bias("f32")}
+        line["time_to_bias_ill_conditioned"] = {
+            "workload": "ill_gaussian_d100_N1024: randomly rotated Gaussian, covariance eigenvalues ~ Gamma(0.5, 1) "
+                        "(condition ~1e5), closed-form moments, automatic switch",
+            "criterion": "first step with b2_max < 0.01",
+            "paper_laps_grads_context": 308,
+            "f64": time_to_bias("f64", target="ill"), "f32": time_to_bias("f32", target="ill")}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, **CPU_SAMPLE[args.workload])
     print(json.dumps(line))

@@ -79,8 +79,19 @@ typedef enum { LAPS_F64 = 0, LAPS_F32 = 1, LAPS_MIXED_BF16 = 2 } laps_precision;
  *                                                scal[1] = lambda
  *   LAPS_CALLBACK    a caller-supplied log p (the method's general input: any
  *                    differentiable log density).  cb and cb_user below.
+ *   LAPS_GAUSS_DENSE zero-mean Gaussian with a dense precision matrix A:
+ *                    log p = -x^T A x / 2.   data[0] = A [d][d] (double,
+ *                    row-major, symmetric positive definite); d <= 512,
+ *                    LAPS_F64 or LAPS_F32 state, MN2 adjusted integrator.
  * Target data must stay valid and unchanged while a context uses it. */
-typedef enum { LAPS_GAUSS_DIAG = 0, LAPS_LOGREG = 1, LAPS_STOCHVOL = 2, LAPS_PHI4 = 3, LAPS_CALLBACK = 4 } laps_target_kind;
+typedef enum {
+  LAPS_GAUSS_DIAG = 0,
+  LAPS_LOGREG = 1,
+  LAPS_STOCHVOL = 2,
+  LAPS_PHI4 = 3,
+  LAPS_CALLBACK = 4,
+  LAPS_GAUSS_DENSE = 5
+} laps_target_kind;
 
 /* Gradient callback of a LAPS_CALLBACK target.  The library calls it on the
  * host thread that enqueues a step, each time the ensemble needs log p and its

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liblaps_hip.so")
 OBJ = os.path.join(PKG, "_build")
 SOURCES = ["laps_api.hip", "laps_local.hip", "laps_local_gauss.hip", "laps_local_sv.hip", "laps_local_phi4.hip",
-           "laps_control.hip", "laps_logreg.hip", "laps_rng.hip"]
+           "laps_control.hip", "laps_logreg.hip", "laps_dense.hip", "laps_rng.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-pass-failed", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

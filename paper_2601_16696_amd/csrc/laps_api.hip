@@ -157,7 +157,7 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape
 bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
   const bool dbl = cfg->prec == LAPS_F64;
   if (is_local(tg->kind)) return local_shape(tg->kind, dbl, cfg->n_chains, cfg->d, cfg->team_lanes, s);
-  if (tg->kind == LAPS_LOGREG || tg->kind == LAPS_CALLBACK) {
+  if (tg->kind == LAPS_LOGREG || tg->kind == LAPS_CALLBACK || tg->kind == LAPS_GAUSS_DENSE) {
     // per-chain update kernels: one oct per lane, up to 64 lanes
     const int64_t octs = (cfg->d + 7) / 8;
     if (cfg->d > (tg->kind == LAPS_LOGREG ? 320 : 512)) return false;
@@ -228,6 +228,9 @@ Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
   } else if (tg->kind == LAPS_CALLBACK) {
     // one partial-sum "split": the callback's g and log p
     lr = logreg_layout(cfg->prec == LAPS_F64 ? 0 : 1, 0, d, N, ld, 1).total;
+  } else if (tg->kind == LAPS_GAUSS_DENSE) {
+    // one partial-sum split, then the precision matrix in the state type
+    lr = logreg_layout(cfg->prec == LAPS_F64 ? 0 : 1, 0, d, N, ld, 1).total + (size_t)round_up(d * d * rs, 256);
   }
   L.packed = c.take(lr);
   const int64_t P = cfg->full_rank_probes;
@@ -280,13 +283,16 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
                LAPS_EUNSUPPORTED;
       break;
     case LAPS_CALLBACK:
-      if (!tg->cb) return why = "a callback target needs cb", LAPS_EINVAL;
-      if (cfg->prec == LAPS_MIXED_BF16) return why = "a callback target runs in LAPS_F64 or LAPS_F32", LAPS_EUNSUPPORTED;
-      if (cfg->d > 512) return why = "a callback target supports d <= 512", LAPS_EUNSUPPORTED;
+    case LAPS_GAUSS_DENSE:
+      if (tg->kind == LAPS_CALLBACK && !tg->cb) return why = "a callback target needs cb", LAPS_EINVAL;
+      if (tg->kind == LAPS_GAUSS_DENSE && !tg->data[0]) return why = "a dense Gaussian needs data[0] = A", LAPS_EINVAL;
+      if (cfg->prec == LAPS_MIXED_BF16)
+        return why = "callback and dense Gaussian targets run in LAPS_F64 or LAPS_F32", LAPS_EUNSUPPORTED;
+      if (cfg->d > 512) return why = "callback and dense Gaussian targets support d <= 512", LAPS_EUNSUPPORTED;
       // same update kernels as logistic regression, so the same MN4 restriction
       if (integ_for(cfg) == 2)
-        return why = "a callback target with the MN4 integrator (d > 200 or integrator_adj = 2) is disabled; set "
-                     "integrator_adj = 1",
+        return why = "callback and dense Gaussian targets with the MN4 integrator (d > 200 or integrator_adj = 2) "
+                     "are disabled; set integrator_adj = 1",
                LAPS_EUNSUPPORTED;
       break;
     default:
@@ -349,7 +355,7 @@ LogregArgs logreg_args(laps_ctx *c, int gate) {
   a.N = c->cfg.n_chains;
   a.d = c->cfg.d;
   a.ld = c->ld;
-  if (c->tg.kind == LAPS_CALLBACK) {
+  if (c->tg.kind == LAPS_CALLBACK || c->tg.kind == LAPS_GAUSS_DENSE) {
     a.n = 0;
     a.S = 1;
     a.NB = 0;
@@ -479,7 +485,9 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
   int cb_rc = 0;
   // the ensemble gradient: the logistic-regression kernels, or the caller's
   // callback writing the single partial-sum split
+  const bool dense = c->tg.kind == LAPS_GAUSS_DENSE;
   auto grad = [&](const LogregArgs &a) -> hipError_t {
+    if (dense) return launch_dense_grad(prec == LAPS_F64 ? 0 : 1, a, c->stream);
     if (!cb) return launch_logreg_grad(prec, a, c->stream);
     const LrOffsets off = logreg_layout(c->dbl ? 0 : 1, 0, a.d, a.N, a.ld, 1);
     cb_rc = c->tg.cb(c->tg.cb_user, c->x, a.scratch + off.Gp, reinterpret_cast<double *>(a.scratch + off.lp), a.N,
@@ -490,7 +498,8 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
   if (kk == KK_INIT) {
     LogregArgs a = logreg_args(c, 0);
     a.u0 = u0;
-    if (!cb && prec != LAPS_F64 && !c->packed_ok) e = launch_logreg_pack(a, c->stream);
+    if (dense && !c->packed_ok) e = launch_dense_pack(prec == LAPS_F64 ? 0 : 1, a, c->stream);
+    if (!cb && !dense && prec != LAPS_F64 && !c->packed_ok) e = launch_logreg_pack(a, c->stream);
     if (e == hipSuccess) c->packed_ok = true;
     if (e == hipSuccess) e = grad(a);
     if (e == hipSuccess) e = upd(a, LR_INIT, 0, 0);
@@ -514,7 +523,7 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     c->err = g_last_global = "gradient callback returned " + std::to_string(cb_rc);
     return LAPS_EDEVICE;
   }
-  return fail(c, e, cb ? "update kernels" : "logistic-regression kernels");
+  return fail(c, e, cb ? "update kernels" : dense ? "dense Gaussian kernels" : "logistic-regression kernels");
 }
 
 }  // namespace
@@ -983,6 +992,9 @@ extern "C" laps_status laps_time_gradient(laps_ctx *c, int32_t n_reps, float *av
       a.logp_out = c->logp;
       a.g_out = c->g;
       e = launch_local(c->tg.kind, c->dbl, c->Q, KK_EVAL, a, c->grid_full, c->block, c->shmem, c->stream);
+    } else if (c->tg.kind == LAPS_GAUSS_DENSE) {
+      LogregArgs a = logreg_args(c, 0);
+      e = launch_dense_grad(c->dbl ? 0 : 1, a, c->stream);
     } else if (c->tg.kind == LAPS_CALLBACK) {
       LogregArgs a = logreg_args(c, 0);
       const LrOffsets off = logreg_layout(c->dbl ? 0 : 1, 0, a.d, a.N, a.ld, 1);

@@ -162,5 +162,9 @@ void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int &S, int &NB, i
 hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s);
 hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s);
 hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, size_t shmem, hipStream_t s);
+// Dense-precision Gaussian: the precision matrix copied in the state type
+// after the single partial-sum split of the scratch, and its gradient kernel.
+hipError_t launch_dense_pack(int prec, const LogregArgs &a, hipStream_t s);
+hipError_t launch_dense_grad(int prec, const LogregArgs &a, hipStream_t s);
 
 }  // namespace laps

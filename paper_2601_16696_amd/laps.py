@@ -16,9 +16,10 @@ LIB_PATH = os.path.join(_HERE, "liblaps_hip.so")
 
 OK, EINVAL, EDEVICE, ENONFINITE, EPHASE, EWORKSPACE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 F64, F32, MIXED_BF16 = 0, 1, 2
-GAUSS_DIAG, LOGREG, STOCHVOL, PHI4, CALLBACK = 0, 1, 2, 3, 4
+GAUSS_DIAG, LOGREG, STOCHVOL, PHI4, CALLBACK, GAUSS_DENSE = 0, 1, 2, 3, 4, 5
 PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, F64: F64, F32: F32, MIXED_BF16: MIXED_BF16}
-KINDS = {"gauss": GAUSS_DIAG, "logreg": LOGREG, "stochvol": STOCHVOL, "phi4": PHI4, "callback": CALLBACK}
+KINDS = {"gauss": GAUSS_DIAG, "logreg": LOGREG, "stochvol": STOCHVOL, "phi4": PHI4, "callback": CALLBACK,
+         "gauss_dense": GAUSS_DENSE}
 # laps_grad_cb: (user, x_dev, g_dev, logp_dev, n_chains, d, ld, stream) -> int
 GRAD_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                            ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p)
@@ -179,6 +180,10 @@ class Target:
             s.data[0] = tX.data_ptr()
             s.data[1] = ty.data_ptr()
             s.dims[0] = int(X.shape[0])
+        elif self.kind == GAUSS_DENSE:
+            t = torch.as_tensor(np.ascontiguousarray(w["prec"], dtype=np.float64), device=device)
+            self.keep.append(t)
+            s.data[0] = t.data_ptr()
         elif self.kind == CALLBACK:
             self._set_callback(w["fn"])
             s.cb = ctypes.cast(self._cb, ctypes.c_void_p)

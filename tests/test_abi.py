@@ -187,3 +187,17 @@ def test_full_rank_probes_validation(L):
     for bad in (-1, 1025):
         c.full_rank_probes = bad
         assert _ws(L, c, t)[0] == L.EINVAL
+
+
+def test_dense_gauss_validation(L):
+    c, t = _cfg_target(L, kind=L.GAUSS_DENSE, d=100)
+    assert _ws(L, c, t)[0] == L.OK
+    t.data[0] = 0
+    assert _ws(L, c, t)[0] == L.EINVAL
+    c, t = _cfg_target(L, kind=L.GAUSS_DENSE, d=300)
+    assert _ws(L, c, t)[0] == L.EUNSUPPORTED      # MN4 selected for d > 200
+    c.integrator_adj = 1
+    st, n = _ws(L, c, t)
+    assert st == L.OK and n >= 300 * 300 * 8      # the precision matrix is copied into the workspace
+    c.prec = L.MIXED_BF16
+    assert _ws(L, c, t)[0] == L.EUNSUPPORTED

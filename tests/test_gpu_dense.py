@@ -1,0 +1,97 @@
+"""The dense-precision Gaussian (the rotated ill-conditioned Gaussian) on the
+GPU against the oracle: gradients and log p at the start, then unadjusted
+steps and MAMS transitions, FP64 and FP32 state, on ragged shapes (d not a
+multiple of the 16-wide tiles or the 4-wide input groups, chains not a
+multiple of the 64-chain workgroups)."""
+import numpy as np
+import pytest
+
+from paper_2601_16696_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "gpu tests need a GPU"
+    from paper_2601_16696_amd import laps
+    laps.lib()
+    return laps
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    return oracle
+
+
+def _rel_rows(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+SHAPES = [(70, 37), (64, 100), (130, 16), (40, 203)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("N,d", SHAPES)
+def test_initial_gradient_and_logp(gpu, orc, prec, N, d):
+    import torch
+    w = workloads.ill_gaussian(n_chains=N, d=d)
+    s = gpu.Sampler(w, prec, switch_policy=1, max_steps_unadj=10, integrator_adj=1)
+    torch.cuda.synchronize()
+    ot = orc.Target.from_workload(w)
+    x = s.positions().cpu().numpy().astype(np.float64)
+    ref = [ot.logp_grad(r) for r in x]
+    g = s.buffer("g").cpu().numpy()[:, :d].astype(np.float64)
+    lp = s.buffer("logp").cpu().numpy()
+    gref = np.array([r[1] for r in ref])
+    lref = np.array([r[0] for r in ref])
+    # sums of d products: error within about d units of rounding of sum_k |A_ik x_k|
+    # (FP32 also rounds A to float)
+    gtol = 1e-12 if prec == "f64" else 2.0 * (d + 1) * 2.0 ** -24
+    scale = np.abs(w["prec"]) @ np.abs(x.T)  # sum_k |A_ik x_k| per (i, chain)
+    assert np.all(np.abs(g - gref) <= gtol * scale.T + 1e-300)
+    ltol = gtol
+    lscale = 0.5 * np.einsum("mi,mi->m", np.abs(x), scale.T)
+    assert np.all(np.abs(lp - lref) <= ltol * lscale)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("N,d", [(70, 37), (64, 100)])
+def test_steps_and_transitions(gpu, orc, prec, N, d):
+    import torch
+    w = workloads.ill_gaussian(n_chains=N, d=d)
+    cfg = dict(switch_policy=1, max_steps_unadj=15, max_steps_total=15 + 15 * 3, integrator_adj=1)
+    s = gpu.Sampler(w, prec, **cfg)
+    o = orc.Ensemble(orc.Target.from_workload(w), N, w["seed"], **cfg)
+    o.init(w["x0"])
+    replay = prec == "f32"
+    for k in range(15):
+        if replay:
+            st = s.stats()
+            o.set_hyper(st["eps"], st["L"])
+        s.step_unadjusted(1)
+        o.step_unadjusted(1)
+        if not replay:
+            sg, so = s.stats(), o.stats()
+            for key in ("eps", "L", "dtilde"):
+                assert abs(sg[key] - so[key]) <= 1e-9 * abs(so[key]), (k, key, sg[key], so[key])
+    x = s.positions().cpu().numpy()
+    assert np.max(_rel_rows(x, o.array("x"))) < TOL[prec]
+    flipped = np.zeros(N, dtype=bool)
+    for k in range(2):
+        if replay and k > 0:
+            o.set_hyper(s.stats()["eps"], 0.0)
+        s.step_adjusted(1)
+        o.step_adjusted(1)
+        torch.cuda.synchronize()
+        err = _rel_rows(s.positions().cpu().numpy(), o.array("x"))
+        flipped |= err > 1e-2
+    if prec == "f64":
+        assert not flipped.any()
+    assert flipped.mean() <= 0.05
+    err = _rel_rows(s.positions().cpu().numpy(), o.array("x"))
+    assert np.max(err[~flipped]) < TOL[prec]
