@@ -126,7 +126,7 @@ CPU_SAMPLE = {  # about 10 s of single-threaded oracle work on the same workload
     "gauss": dict(n_chains=1024, n_unadj=600, n_adj=4),
     "stochvol": dict(n_chains=512, n_unadj=20, n_adj=1),
     "phi4": dict(n_chains=512, n_unadj=20, n_adj=1),
-    "ill_gauss": dict(n_chains=1024, n_unadj=500, n_adj=4),
+    "ill_gauss": dict(n_chains=1024, n_unadj=1000, n_adj=8),
 }
 
 

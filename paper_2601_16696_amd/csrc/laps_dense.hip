@@ -2,15 +2,16 @@
 // ill-conditioned Gaussian of section "Results"): log p = -x^T A x / 2 and
 // g = -A x for every chain, as one matrix product X A on the matrix cores.
 //
-// A workgroup of 4 wavefronts holds 64 chains, 16 per wavefront.  Per
-// wavefront the output is a row of 16 x 16 tiles (chains x dims), eight tiles
-// per pass over the input dims, four input dims per instruction:
+// A workgroup holds 16 chains; each of its wavefronts (up to 16) computes
+// 16-wide output tiles t = w, w + nw, ... of those chains, four input dims per
+// instruction:
 //   FP64 state: v_mfma_f64_16x16x4_f64; FP32 state: v_mfma_f32_16x16x4_f32.
 // Lane l supplies X[m0 + l%16][k0 + l/16] and A[k0 + l/16][j0 + l%16]; its
 // results are (chain, dim) = (m0 + l/16 + 4i, j0 + l%16) for FP64 and
 // (m0 + 4(l/16) + i, j0 + l%16) for FP32 (lane layouts measured on the MI355X).
-// log p = x.g / 2 is summed per chain in FP64 over the tiles in dim order,
-// then across the 16 lanes of a chain by xor butterflies (a fixed order).
+// log p = x.g / 2 is summed per chain in FP64 over a wavefront's tiles in
+// order, across the 16 lanes of a chain by xor butterflies, then over the
+// wavefronts in order through LDS (a fixed order throughout).
 // Outputs go to the single partial-sum split that the per-chain update
 // kernels read (g and log p without a prior term).
 #include "laps_internal.hpp"
@@ -39,10 +40,8 @@ struct DenseMfma<float> {
   static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
-constexpr int kDenseTiles = 8;  // 16-wide output tiles per pass
-
 template <class Real>
-__global__ void __launch_bounds__(256) k_dense_grad(LogregArgs a) {
+__global__ void __launch_bounds__(1024) k_dense_grad(LogregArgs a) {
   if (a.gate != 0) {
     const DevHyper *H = a.hyp;
     if (a.gate == 1 && H->phase != PH_UNADJ) return;
@@ -50,9 +49,10 @@ __global__ void __launch_bounds__(256) k_dense_grad(LogregArgs a) {
   }
   typedef DenseMfma<Real> M;
   typedef typename M::acc_t acc_t;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double lsh[16 * 16];  // [wavefront][chain]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t N = a.N, d = a.d, ld = a.ld;
-  const int64_t m0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  const int64_t m0 = (int64_t)blockIdx.x * 16;
   const LrOffsets off = logreg_layout(sizeof(Real) == 8 ? 0 : 1, 0, d, N, ld, 1);
   const Real *X = static_cast<const Real *>(a.x);
   const Real *A = reinterpret_cast<const Real *>(a.scratch + off.total);  // [d][d] in the state type
@@ -63,45 +63,54 @@ __global__ void __launch_bounds__(256) k_dense_grad(LogregArgs a) {
   const int jl = lane & 15;             // output dim within a tile
   const int64_t JT = (d + 15) / 16;
   double lp[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t jb = 0; jb < JT; jb += kDenseTiles) {
-    acc_t acc[kDenseTiles];
+  for (int64_t t = wave; t < JT; t += nw) {
+    const int64_t j = t * 16 + jl;
+    acc_t acc = acc_t{0, 0, 0, 0};
+    int64_t k0 = 0;
+    for (; k0 + 16 <= d; k0 += 16) {
+      // four groups of four input dims: their eight loads are issued together
+      Real av[4], bv[4];
 #pragma unroll
-    for (int t = 0; t < kDenseTiles; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    for (int64_t k0 = 0; k0 < d; k0 += 4) {
+      for (int u = 0; u < 4; ++u) {
+        const int64_t k = k0 + 4 * u + kl;
+        av[u] = ma < N ? X[ma * ld + k] : Real(0);
+        bv[u] = j < d ? A[k * d + j] : Real(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = M::mma(av[u], bv[u], acc);
+    }
+    for (; k0 < d; k0 += 4) {
       const int64_t k = k0 + kl;
       const Real av = (ma < N && k < d) ? X[ma * ld + k] : Real(0);
-#pragma unroll
-      for (int t = 0; t < kDenseTiles; ++t) {
-        const int64_t j = (jb + t) * 16 + jl;
-        if (jb + t < JT) {
-          const Real bv = (k < d && j < d) ? A[k * d + j] : Real(0);
-          acc[t] = M::mma(av, bv, acc[t]);
-        }
-      }
+      const Real bv = (k < d && j < d) ? A[k * d + j] : Real(0);
+      acc = M::mma(av, bv, acc);
     }
+    if (j < d) {
 #pragma unroll
-    for (int t = 0; t < kDenseTiles; ++t) {
-      const int64_t j = (jb + t) * 16 + jl;
-      if (jb + t < JT && j < d) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int64_t m = m0 + M::row(lane, i);
-          if (m < N) {
-            const Real g = -acc[t][i];
-            G[m * ld + j] = g;
-            lp[i] += (double)X[m * ld + j] * (double)g;
-          }
+      for (int i = 0; i < 4; ++i) {
+        const int64_t m = m0 + M::row(lane, i);
+        if (m < N) {
+          const Real g = -acc[i];
+          G[m * ld + j] = g;
+          lp[i] += (double)X[m * ld + j] * (double)g;
         }
       }
     }
   }
-  // per chain: the 16 lanes of equal lane / 16 hold its dims
+  // per chain: the 16 lanes of equal lane / 16 hold a wavefront's dims ...
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
     for (int msk = 1; msk < 16; msk <<= 1) lp[i] += __shfl_xor(lp[i], msk);
-    const int64_t m = m0 + M::row(lane, i);
-    if (jl == 0 && m < N) LP[m] = 0.5 * lp[i];
+    if (jl == 0) lsh[wave * 16 + M::row(lane, i)] = lp[i];
+  }
+  __syncthreads();
+  // ... and the wavefronts' sums are added in wavefront order
+  if (threadIdx.x < 16) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += lsh[w * 16 + threadIdx.x];
+    const int64_t m = m0 + threadIdx.x;
+    if (m < N) LP[m] = 0.5 * s;
   }
 }
 
@@ -125,11 +134,13 @@ hipError_t launch_dense_pack(int prec, const LogregArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_dense_grad(int prec, const LogregArgs &a, hipStream_t s) {
-  const dim3 grid((unsigned)((a.N + 63) / 64));
+  // 16 chains per workgroup, one wavefront per output tile up to 16
+  const int64_t JT = (a.d + 15) / 16;
+  const dim3 grid((unsigned)((a.N + 15) / 16)), block((unsigned)(64 * (JT < 16 ? JT : 16)));
   if (prec == 0)
-    hipLaunchKernelGGL(k_dense_grad<double>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_dense_grad<double>, grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL(k_dense_grad<float>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_dense_grad<float>, grid, block, 0, s, a);
   return hipGetLastError();
 }
 
