@@ -366,16 +366,27 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
   // forward fragments (2 KC x 64) precede the backward ones.  A wavefront's 64
   // fragments of one instruction lie in one block, so the block test is
   // uniform per wavefront; lanes 0..15 of wavefront 0 also stage the labels.
+  // Both packed forms have 2 KC x 64 fragments per block, so a fragment's
+  // source is a uniform base (advanced by two blocks per iteration) plus a
+  // loop-invariant per-thread offset.
+  constexpr int kBlk = 2 * KC * 64;
+  const bf16x8 *baseF = XF + (int64_t)b0 * kBlk, *baseB = XB + (int64_t)b0 * kBlk;
+  int offk[kPer], halfk[kPer];
+  bool fwdk[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int c = tid + 512 * k;
+    const int half = c / kFrag, f = c - half * kFrag;
+    halfk[k] = half;
+    fwdk[k] = f < kBlk;
+    offk[k] = half * kBlk + (f < kBlk ? f : f - kBlk);
+  }
   auto stage = [&](int it, int buf) {
+    const int64_t step = (int64_t)it * 2 * kBlk;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int c = tid + 512 * k;
-      const int half = c / kFrag, f = c - half * kFrag;
-      const int64_t blk = b0 + 2 * it + half;
-      if (blk < b1) {
-        const bf16x8 *src = f < 2 * KC * 64 ? XF + blk * 2 * KC * 64 + f : XB + blk * 2 * KC * 64 + (f - 2 * KC * 64);
-        lds_dma16(src, lds + buf * kBuf + (c - lane));
-      }
+      if (b0 + 2 * it + halfk[k] < b1)
+        lds_dma16((fwdk[k] ? baseF : baseB) + step + offk[k], lds + buf * kBuf + 512 * k + 64 * wave);
     }
     if (tid < 16) {
       const int64_t blk = b0 + 2 * it + (tid >> 3);
@@ -424,14 +435,13 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
-  // half 1 hands its partial sums to half 0 through LDS (fixed order: half 0 + half 1)
-  float *red = reinterpret_cast<float *>(lds);
-  double *lred = reinterpret_cast<double *>(red + 4 * 64 * 8 * KC);
+  // half 1 hands its partial sums to half 0 through LDS (fixed order: half 0 + half 1);
+  // a lane's four values of a tile are consecutive dims, moved as one 16-byte word
+  f32x4 *red = reinterpret_cast<f32x4 *>(lds);
+  double *lred = reinterpret_cast<double *>(red + 4 * 2 * KC * 64);
   if (rh == 1) {
 #pragma unroll
-    for (int dc = 0; dc < 2 * KC; ++dc)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) red[((cg * 2 * KC + dc) * 4 + i) * 64 + lane] = gacc[dc][i];
+    for (int dc = 0; dc < 2 * KC; ++dc) red[(cg * 2 * KC + dc) * 64 + lane] = gacc[dc];
     lred[cg * 64 + lane] = lacc;
   }
   __syncthreads();
@@ -439,12 +449,13 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
     float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
     if (mval) {
 #pragma unroll
-      for (int dc = 0; dc < 2 * KC; ++dc)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int64_t dd = 16 * dc + 4 * q + i;
-          if (dd < ld) Gp[dd] = gacc[dc][i] + red[((cg * 2 * KC + dc) * 4 + i) * 64 + lane];
+      for (int dc = 0; dc < 2 * KC; ++dc) {
+        const int64_t dd = 16 * dc + 4 * q;  // ld is a multiple of 8, so dd < ld covers dd .. dd + 3
+        if (dd < ld) {
+          const f32x4 v = gacc[dc] + red[(cg * 2 * KC + dc) * 64 + lane];
+          *reinterpret_cast<f32x4 *>(Gp + dd) = v;
         }
+      }
     }
     lacc += lred[cg * 64 + lane];
     lacc += __shfl_xor(lacc, 16);
