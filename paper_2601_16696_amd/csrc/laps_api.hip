@@ -150,7 +150,7 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape
   }
   s.shmem = fixed + body(block);
   s.shmem_sig = s.shmem + (size_t)ld * rs;
-  s.nb = (int)((d + 31) / 32);
+  s.nb = (int)((d + fin_dims(d) - 1) / fin_dims(d));
   return true;
 }
 
@@ -172,7 +172,7 @@ bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
     s.split = false;
     s.shmem = 2 * kRedSlots * sizeof(double) + (size_t)4 * 8 * T * 8;
     s.shmem_sig = s.shmem;
-    s.nb = (int)((cfg->d + 31) / 32);
+    s.nb = (int)((cfg->d + fin_dims(cfg->d) - 1) / fin_dims(cfg->d));
     return true;
   }
   return false;

@@ -166,31 +166,40 @@ __device__ void ctl_unadj_body(const CtlArgs &c, double *sh, double &mean_sh) {
   if ((c.switch_policy == 0 && H->switch_ready) || H->t >= c.max_unadj) H->phase = PH_SWITCH_PENDING;
 }
 
-// 32 dimensions per 1024-thread block: lane group rg (0..31) of dimension
-// column dl sums partial rows rg, rg + 32, ...; the 32 group sums are then
-// added in group order, so the result does not depend on timing.  The moving
-// window is reduced the same way over its slots.
-constexpr int kFinDims = 32, kFinGroups = 32;
-
+// DIMS dimensions per 1024-thread block (8 up to d = 1024, else 32): row
+// group rg (0 .. 1024/DIMS - 1) of dimension column dl sums partial rows rg,
+// rg + groups, ...; the group sums are combined first inside each wavefront
+// by xor butterflies over the group bits, then over the wavefronts in order
+// through LDS, so the result does not depend on timing.  The moving window is
+// reduced the same way over its slots.
+template <int DIMS>
 __device__ __forceinline__ void fin_combine(double (&v)[4], double *sh, int dl, int rg) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) sh[(rg * 4 + k) * kFinDims + dl] = v[k];
+  for (int msk = DIMS; msk < 64; msk <<= 1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], msk);
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) < DIMS)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[(wave * 4 + k) * DIMS + dl] = v[k];
   __syncthreads();
   if (rg == 0) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       double s = 0.0;
-      for (int g = 0; g < kFinGroups; ++g) s += sh[(g * 4 + k) * kFinDims + dl];
+      for (int w = 0; w < nw; ++w) s += sh[(w * 4 + k) * DIMS + dl];
       v[k] = s;
     }
   }
   __syncthreads();
 }
 
+template <int DIMS>
 __global__ void __launch_bounds__(1024) k_finalize(CtlArgs c, int mode) {
+  constexpr int kFinDims = DIMS, kFinGroups = 1024 / DIMS;
   const DevHyper *H = c.hyp;
   if (mode == FIN_UNADJ && H->phase != PH_UNADJ) return;
-  __shared__ double sh[kFinGroups * 4 * kFinDims];
+  __shared__ double sh[16 * 4 * kFinDims];
   __shared__ double bsh[16 * 4];
   __shared__ double mu_sh[kFinDims];
   const int dl = threadIdx.x % kFinDims, rg = threadIdx.x / kFinDims;
@@ -214,7 +223,7 @@ __global__ void __launch_bounds__(1024) k_finalize(CtlArgs c, int mode) {
       for (int k = 0; k < 4; ++k) v[k] += P[k * ld];
     }
   }
-  fin_combine(v, sh, dl, rg);
+  fin_combine<DIMS>(v, sh, dl, rg);
   double Dp = 0.0, vp = 0.0, wd = -INFINITY;
   const bool full = mode == FIN_UNADJ && (H->ring_count + 1 >= c.Tw);
   if (rg == 0 && act) {
@@ -250,7 +259,7 @@ __global__ void __launch_bounds__(1024) k_finalize(CtlArgs c, int mode) {
       }
       for (; k < c.Tw; k += kFinGroups) w1[0] += c.ring[k * ld + i];
     }
-    fin_combine(w1, sh, dl, rg);
+    fin_combine<DIMS>(w1, sh, dl, rg);
     if (rg == 0) mu_sh[dl] = w1[0] / (double)c.Tw;
     __syncthreads();
     const double mu = mu_sh[dl];
@@ -272,7 +281,7 @@ __global__ void __launch_bounds__(1024) k_finalize(CtlArgs c, int mode) {
         w2[0] += e * e;
       }
     }
-    fin_combine(w2, sh, dl, rg);
+    fin_combine<DIMS>(w2, sh, dl, rg);
     if (rg == 0 && act) {
       wd = sqrt(w2[0] / (double)(c.Tw - 1)) / mu;
       c.wdelta[i] = wd;
@@ -505,7 +514,10 @@ hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const CtlArgs &c, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(c.nb), dim3(1024), 0, s, c, mode);
+  if (fin_dims(c.d) == 8)
+    hipLaunchKernelGGL(k_finalize<8>, dim3(c.nb), dim3(1024), 0, s, c, mode);
+  else
+    hipLaunchKernelGGL(k_finalize<32>, dim3(c.nb), dim3(1024), 0, s, c, mode);
   return hipGetLastError();
 }
 hipError_t launch_ctl_init(const CtlArgs &c, hipStream_t s) {

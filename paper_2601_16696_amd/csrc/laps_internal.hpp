@@ -63,6 +63,9 @@ struct CtlArgs {
 };
 
 enum { FIN_INIT = 0, FIN_UNADJ = 1 };
+// dimensions per workgroup of the statistics pass (its block count is
+// ceil(d / fin_dims(d)))
+__host__ __device__ inline int fin_dims(int64_t d) { return d <= 1024 ? 8 : 32; }
 constexpr int kProbeChunk = 512;  // chains per partial projection of the full-rank loss
 
 // Launchers (return hipSuccess or the launch error).

@@ -311,26 +311,30 @@ __device__ __forceinline__ void lr_block_lean(const bf16x8 *L, const float *Y, i
   const float4 y0 = *reinterpret_cast<const float4 *>(Y + 4 * q);
   const float4 y1 = *reinterpret_cast<const float4 *>(Y + 16 + 4 * q);
   const float yv[2][4] = {{y0.x, y0.y, y0.z, y0.w}, {y1.x, y1.y, y1.z, y1.w}};
-  // With the packed label ym = y - 1/2 and s = 1/(1 + e^{-|z|}):
-  //   r = y - sigmoid(z) = ym - copysign(s - 1/2, z)   (s - 1/2 is exact),
-  //   y z - softplus(z) = ym z - |z|/2 - log(1 + e^{-|z|}),
-  // the lane's eight logs taken as one log of their product (factors in (1, 2])
+  // The products carry z' = z log2(e) (theta is scaled before its hi/lo
+  // split), so e^{-|z|} is one base-2 exponential.  With the packed label
+  // ym = y - 1/2 and s = 1/(1 + e^{-|z|}):
+  //   r = y - sigmoid(z) = ym - copysign(s - 1/2, z')   (s - 1/2 is exact),
+  //   y z - softplus(z) = ln2 (ym z' - |z'|/2) - log(1 + e^{-|z|}),
+  // with ym z' and |z'| summed apart and the lane's eight logs taken as one
+  // log of their product (factors in (1, 2])
   bf16x8 rb;
-  float lin = 0.f, prod = 1.f;
+  float la = 0.f, lb = 0.f, prod = 1.f;
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const float zz = z[h][i];
       const bool ok = FULL || (16 * h + 4 * q + i < nvalid);
-      const float e = ok ? __expf(-fabsf(zz)) : 0.f;
+      const float e = ok ? __builtin_amdgcn_exp2f(-fabsf(zz)) : 0.f;
       const float ope = 1.0f + e;
       const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
       rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - copysignf(t, zz) : 0.f);
-      lin += ok ? fmaf(yv[h][i], zz, -0.5f * fabsf(zz)) : 0.f;
+      la += ok ? yv[h][i] * zz : 0.f;
+      lb += ok ? fabsf(zz) : 0.f;
       prod *= ope;
     }
-  lacc += (double)lin - (double)__logf(prod);
+  lacc += 0.6931471805599453 * ((double)la - 0.5 * (double)lb) - (double)__logf(prod);
 #pragma unroll
   for (int dc = 0; dc < 2 * KC; ++dc) {
     const bf16x8 bfr = L[2 * KC * 64 + dc * 64 + lane];
@@ -402,7 +406,9 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
       const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (mval && d4 < ld) v = *reinterpret_cast<const float4 *>(X + m * ld + d4);
-      const float f[4] = {v.x, v.y, v.z, v.w};
+      // theta log2(e), split into bf16 hi + lo
+      const float f[4] = {v.x * 1.4426950408889634f, v.y * 1.4426950408889634f, v.z * 1.4426950408889634f,
+                          v.w * 1.4426950408889634f};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const __bf16 hi = (__bf16)f[i];
