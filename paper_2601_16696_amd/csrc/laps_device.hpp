@@ -96,27 +96,60 @@ __device__ __forceinline__ double mh_uniform(uint64_t seed, uint64_t m, uint64_t
 
 // ---------------------------------------------------------------------------
 // Team reductions.  A team of T lanes owns one chain: T <= 64 is an aligned
-// lane group inside a wavefront (xor butterflies, no barrier); T > 64 is the
+// lane group inside a wavefront (butterflies, no barrier); T > 64 is the
 // whole workgroup (butterfly per wavefront, then a fixed-order sum over
 // wavefronts through LDS, double-buffered so one barrier suffices).  Every
 // lane ends with the identical value, and the order of additions is fixed.
 // ---------------------------------------------------------------------------
 constexpr int kRedSlots = 16 * 8;  // doubles per buffer: 16 wavefronts x 8 values
 
+// A double moved between lanes by a DPP row permutation (CTRL: 0x00-0xFF quad
+// permutation, 0x140 mirror of the 16-lane row, 0x141 mirror of each 8-lane half).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over each aligned group of T lanes (T a power of two up to 64), the same
+// value in every lane of a group.  Masks of 16 and 32 are xor shuffles; below
+// 16 the partners are the DPP row mirror (i <-> 15 - i), the half-row mirror
+// (i <-> 7 - i) and the quad swaps, which pair lanes as the xor butterfly does
+// at the granularity reached so far, without a trip through LDS.  Every pair
+// is added as (own + partner), so both partners hold identical sums.
 template <int NV>
-__device__ __forceinline__ void team_sum(double (&v)[NV], int T, double *red, int &slot) {
-  if (T <= 64) {
-    for (int msk = T >> 1; msk >= 1; msk >>= 1) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], msk);
-    }
-    return;
-  }
-#pragma unroll
-  for (int msk = 32; msk >= 1; msk >>= 1) {
+__device__ __forceinline__ void group_sum(double (&v)[NV], int T) {
+  for (int msk = T >> 1; msk >= 16; msk >>= 1) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], msk);
   }
+  if (T >= 16) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0x140>(v[k]);
+  }
+  if (T >= 8) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0x141>(v[k]);
+  }
+  if (T >= 4) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0x4E>(v[k]);  // quad lanes (2, 3, 0, 1)
+  }
+  if (T >= 2) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0xB1>(v[k]);  // quad lanes (1, 0, 3, 2)
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void team_sum(double (&v)[NV], int T, double *red, int &slot) {
+  if (T <= 64) {
+    group_sum<NV>(v, T);
+    return;
+  }
+  group_sum<NV>(v, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = T >> 6;
   const int w0 = (wave / nw) * nw;  // first wavefront of this lane's team
   double *buf = red + slot * kRedSlots;
