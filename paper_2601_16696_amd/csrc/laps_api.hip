@@ -91,7 +91,7 @@ bool is_local(int kind) { return kind == LAPS_GAUSS_DIAG || kind == LAPS_STOCHVO
 // work is shared by 8 Q coordinates per lane; only chains longer than 64 lanes
 // x Q_max octs use multi-wavefront teams.  FP64 state keeps up to 2 octs per
 // lane in registers, FP32 up to 6.
-bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape &s) {
+bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape &s, int block_threads = 0) {
   const int64_t octs = (d + 7) / 8;
   // a phi^4 lattice whose rows are not whole octs runs one oct per lane
   const int64_t side = kind == LAPS_PHI4 ? (int64_t)llround(sqrt((double)d)) : 0;
@@ -131,11 +131,8 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape
   // Up to 256 threads per workgroup; fewer when the teams' chain copies would
   // take more than 56 KiB of LDS (which would cap the resident wavefronts).
   int64_t block = T <= 64 ? 256 : T;
-  if (const char *e = getenv("LAPS_LOCAL_BLOCK")) {
-    // workgroup size override (64, 128 or 256 threads) for teams inside a wavefront
-    const int64_t b = atol(e);
-    if (T <= 64 && (b == 64 || b == 128 || b == 256)) block = b;
-  }
+  // workgroup size override (64, 128 or 256 threads) for teams inside a wavefront
+  if (T <= 64 && (block_threads == 64 || block_threads == 128 || block_threads == 256)) block = block_threads;
   while (T <= 64 && block > T && block > 64 && fixed + body(block) + (size_t)ld * rs > 56 * 1024) block >>= 1;
   s.block = (int)block;
   s.tpw = (int)(block / T);
@@ -156,7 +153,8 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape
 
 bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
   const bool dbl = cfg->prec == LAPS_F64;
-  if (is_local(tg->kind)) return local_shape(tg->kind, dbl, cfg->n_chains, cfg->d, cfg->team_lanes, s);
+  if (is_local(tg->kind))
+    return local_shape(tg->kind, dbl, cfg->n_chains, cfg->d, cfg->team_lanes, s, cfg->block_threads);
   if (tg->kind == LAPS_LOGREG || tg->kind == LAPS_CALLBACK || tg->kind == LAPS_GAUSS_DENSE) {
     // per-chain update kernels: one oct per lane, up to 64 lanes
     const int64_t octs = (cfg->d + 7) / 8;
@@ -223,7 +221,7 @@ Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
   size_t lr = 0;
   if (tg->kind == LAPS_LOGREG) {
     int S, NB, bps;
-    logreg_splits(tg->dims[0], N, cfg->prec, d, S, NB, bps);
+    logreg_splits(tg->dims[0], N, cfg->prec, d, cfg->grad_workgroups, S, NB, bps);
     lr = logreg_layout(cfg->prec == LAPS_F64 ? 0 : 1, tg->dims[0], d, N, ld, S).total;
   } else if (tg->kind == LAPS_CALLBACK) {
     // one partial-sum "split": the callback's g and log p
@@ -258,6 +256,11 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
       !(cfg->L_partial_factor > 0.0))
     return why = "non-positive constant in config", LAPS_EINVAL;
   if (cfg->team_lanes < 0) return why = "team_lanes must be >= 0", LAPS_EINVAL;
+  if (!(cfg->block_threads == 0 || cfg->block_threads == 64 || cfg->block_threads == 128 ||
+        cfg->block_threads == 256))
+    return why = "block_threads must be 0, 64, 128 or 256", LAPS_EINVAL;
+  if (cfg->grad_workgroups < 0 || cfg->grad_workgroups > 65536)
+    return why = "grad_workgroups must be in 0..65536", LAPS_EINVAL;
   if (cfg->full_rank_probes < 0 || cfg->full_rank_probes > 1024)
     return why = "full_rank_probes must be in 0..1024", LAPS_EINVAL;
   if (cfg->integrator_adj < 0 || cfg->integrator_adj > 2 || cfg->eevpd_mode < 0 || cfg->eevpd_mode > 1 ||
@@ -362,7 +365,7 @@ LogregArgs logreg_args(laps_ctx *c, int gate) {
     a.bps = 0;
     a.prior = 0;
   } else {
-    logreg_splits(a.n, a.N, c->cfg.prec, a.d, a.S, a.NB, a.bps);
+    logreg_splits(a.n, a.N, c->cfg.prec, a.d, c->cfg.grad_workgroups, a.S, a.NB, a.bps);
     a.prior = 1;
   }
   a.KC = (int)((a.d + 31) / 32);

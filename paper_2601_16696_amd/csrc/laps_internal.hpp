@@ -161,7 +161,8 @@ __host__ __device__ inline LrOffsets logreg_layout(int prec, int64_t n, int64_t 
   return o;
 }
 
-void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int &S, int &NB, int &bps);
+// Row splits of the gradient launch: wgs workgroups aimed for (0: automatic).
+void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int wgs, int &S, int &NB, int &bps);
 hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s);
 hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s);
 hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, size_t shmem, hipStream_t s);

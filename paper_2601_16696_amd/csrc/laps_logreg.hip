@@ -42,13 +42,13 @@ static bool lr_lds_kernel() {
   return v != 0;
 }
 
-void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int &S, int &NB, int &bps) {
+void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int wgs, int &S, int &NB, int &bps) {
   NB = (int)((n + 31) / 32);
   const int64_t groups = (N + 63) / 64;
   // workgroups of one gradient launch: two per CU for the direct-to-LDS bf16
   // kernel (which two workgroups per CU fit), one per CU otherwise
   int64_t target = (prec != 0 && d <= 128 && lr_lds_kernel()) ? 512 : 256;
-  if (const char *e = getenv("LAPS_LR_WGS")) target = atol(e) > 0 ? atol(e) : target;
+  if (wgs > 0) target = wgs;
   int64_t want = target / (groups > 0 ? groups : 1);
   if (want < 1) want = 1;
   if (want > NB) want = NB;

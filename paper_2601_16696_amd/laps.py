@@ -39,7 +39,8 @@ class Config(ctypes.Structure):
                 ("L_partial_factor", ctypes.c_double), ("n_steps_traj", ctypes.c_int32),
                 ("integrator_adj", ctypes.c_int32), ("eevpd_mode", ctypes.c_int32),
                 ("switch_policy", ctypes.c_int32), ("max_steps_unadj", ctypes.c_int64),
-                ("max_steps_total", ctypes.c_int64), ("team_lanes", ctypes.c_int32), ("full_rank_probes", ctypes.c_int32)]
+                ("max_steps_total", ctypes.c_int64), ("team_lanes", ctypes.c_int32), ("full_rank_probes", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("grad_workgroups", ctypes.c_int32)]
 
 
 class TargetS(ctypes.Structure):
@@ -77,6 +78,9 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise LapsError(EUNSUPPORTED, f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                       "(python -m paper_2601_16696_amd.build)")
+    # torch first: its HIP runtime then provides the soname libamdhip64.so.7
+    # that the library links, so the process holds one runtime, not two.
+    _torch()
     L = ctypes.CDLL(LIB_PATH)
     P, I64, I32, U64, U32, D = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
                                 ctypes.c_double)
@@ -425,3 +429,103 @@ def philox_normals(seed: int, n_chains: int, d: int, t: int, tag: int, substep: 
     _check(lib().laps_philox_normals(seed, n_chains, d, t, tag, substep, p, ctypes.c_void_p(out.data_ptr()),
                                      _stream_ptr()))
     return out[:, :d]
+
+
+_LOG_DENSITY_FN = None
+
+
+def log_density(target: "Target", x):
+    """log p of the rows of x ([n, d]) as a differentiable torch function: the
+    forward pass is one launch of the library's target kernel (laps_target_eval,
+    log p and gradient together), the backward pass scales the saved gradient
+    by the incoming one.  For the targets with a standalone evaluation
+    (diagonal Gaussian, stochastic volatility, phi^4)."""
+    global _LOG_DENSITY_FN
+    torch = _torch()
+    if _LOG_DENSITY_FN is None:
+        class _LogDensity(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, xx, tgt):
+                lp, g = tgt.eval(xx, grad=True)
+                ctx.save_for_backward(g)
+                return lp.to(xx.dtype)
+
+            @staticmethod
+            def backward(ctx, gout):
+                (g,) = ctx.saved_tensors
+                return gout[:, None].to(g.dtype) * g, None
+
+        _LOG_DENSITY_FN = _LogDensity
+    return _LOG_DENSITY_FN.apply(x, target)
+
+
+def _shape_candidates(w: dict, prec) -> list:
+    """Launch shapes worth timing for a workload: team widths and workgroup
+    sizes of the per-chain kernels, or gradient workgroup counts for logistic
+    regression (others have one shape)."""
+    kind = KINDS[w["kind"]]
+    if kind in (GAUSS_DIAG, STOCHVOL, PHI4):
+        out = [dict(team_lanes=0, block_threads=0)]
+        for T in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512):
+            for b in ((0, 64, 128) if T <= 64 else (0,)):
+                out.append(dict(team_lanes=T, block_threads=b))
+        return out
+    if kind == LOGREG:
+        return [dict(grad_workgroups=g) for g in (0, 256, 512, 1024)]
+    return [dict()]
+
+
+def _tune_key(w: dict, prec) -> str:
+    n = int(np.asarray(w["X"]).shape[0]) if w["kind"] == "logreg" else 0
+    pname = {F64: "f64", F32: "f32", MIXED_BF16: "bf16"}[PRECISIONS[prec]]
+    return f"{w['kind']}:d={int(w['d'])}:n={n}:N={int(w['n_chains'])}:prec={pname}"
+
+
+def autotune(w: dict, prec="f64", cache: str | None = None, n_steps: int = 20, **cfg) -> dict:
+    """Times n_steps unadjusted steps of every valid launch shape of the
+    workload (after a warm-up) and returns the fastest shape's config fields,
+    with its ms per step.  Results are kept in the JSON file `cache` (if
+    given) under the key (target kind, d, n, N, precision); a cached key is
+    returned without timing.  A fresh search also returns every shape's time
+    under "trials".  The shapes change rounding order only: every
+    one runs the same method."""
+    import json
+    torch = _torch()
+    key = _tune_key(w, prec)
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            table = json.load(f)
+        if key in table:
+            return dict(table[key], cached=True)
+    best, errors, trials = None, [], []
+    base = dict(cfg)
+    base.setdefault("switch_policy", 1)
+    base.setdefault("max_steps_unadj", 10 * n_steps + 10)
+    for cand in _shape_candidates(w, prec):
+        try:
+            s = Sampler(w, prec, **base, **cand)
+        except LapsError as e:
+            errors.append(f"{cand}: {e}")
+            continue  # not a valid shape for this size
+        s.step_unadjusted(2)
+        ms = float("inf")
+        for _ in range(2):  # the faster of two timings, against clock noise
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.step_unadjusted(n_steps)
+            e1.record()
+            e1.synchronize()
+            ms = min(ms, e0.elapsed_time(e1) / n_steps)
+        del s
+        trials.append(dict(cand, ms_per_step=ms))
+        if best is None or ms < best["ms_per_step"]:
+            best = dict(cand, ms_per_step=ms)
+    if best is None:
+        raise LapsError(EUNSUPPORTED, "no valid launch shape: " + "; ".join(errors[:3]))
+    if cache:
+        table[key] = best
+        with open(cache + ".tmp", "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(cache + ".tmp", cache)
+    return dict(best, cached=False, trials=trials)

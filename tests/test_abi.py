@@ -201,3 +201,15 @@ def test_dense_gauss_validation(L):
     assert st == L.OK and n >= 300 * 300 * 8      # the precision matrix is copied into the workspace
     c.prec = L.MIXED_BF16
     assert _ws(L, c, t)[0] == L.EUNSUPPORTED
+
+
+def test_launch_shape_fields_validation(L):
+    c, t = _cfg_target(L, kind=0, N=64, d=40)
+    for b in (0, 64, 128, 256):
+        c.block_threads = b
+        assert _ws(L, c, t)[0] == L.OK
+    c.block_threads = 96
+    assert _ws(L, c, t)[0] == L.EINVAL
+    c.block_threads = 0
+    c.grad_workgroups = -1
+    assert _ws(L, c, t)[0] == L.EINVAL
