@@ -158,6 +158,10 @@ typedef struct {
                                or 64, 128, 256 threads per workgroup */
   int32_t grad_workgroups;  /* logistic regression: 0 = automatic, else the number of workgroups a
                                gradient launch aims for (sets the row splits) */
+  double eps_fixed;         /* 0: the adaptive step size of section "Step size" (the paper's method);
+                               > 0: this step size throughout the unadjusted phase, all else unchanged
+                               (the fixed-step comparison of the step-size appendix); the adjusted
+                               phase starts from it and bisects as usual */
 } laps_config;
 
 /* Snapshot of the device-resident hyperparameters and diagnostics.

@@ -337,6 +337,7 @@ static double *alloc0(int64_t n) { return (double *)calloc((size_t)(n > 0 ? n : 
 
 orc_ctx *orc_create(const orc_config *cfg, const orc_target *tg) {
   if (cfg->d < 2 || cfg->n_chains < 2 || tg->d != cfg->d) return NULL;
+  if (!(cfg->eps_fixed >= 0.0) || !isfinite(cfg->eps_fixed)) return NULL;
   orc_ctx *c = (orc_ctx *)calloc(1, sizeof(orc_ctx));
   c->cfg = *cfg;
   c->tg = *tg;
@@ -453,7 +454,7 @@ int orc_init(orc_ctx *c, const double *x0, const double *u0) {
   }
   ensemble_moments(c);
   /* Algorithm: eps <- 0.01 sqrt(d), L <- eq. (L) on the initial ensemble */
-  c->eps = c->cfg.eps0_factor * sqrt((double)d);
+  c->eps = c->cfg.eps_fixed > 0.0 ? c->cfg.eps_fixed : c->cfg.eps0_factor * sqrt((double)d);
   c->L = c->cfg.alpha * sqrt(c->sum_var);
   c->t = 0;
   c->grads = 1;
@@ -548,7 +549,7 @@ void orc_unadj_control(orc_ctx *c) {
     if (bad) c->status |= ST_NONFINITE;
   }
   c->eevpd_target = orc_F(c->cfg.C * c->dtilde);
-  {
+  if (!(c->cfg.eps_fixed > 0.0)) {
     const double ratio = c->eevpd_target / c->eevpd;
     if (isfinite(ratio) && ratio > 0.0) c->eps *= pow(ratio, 1.0 / 6.0);
     else c->status |= ST_EPS_KEPT;  /* R20 */

@@ -65,6 +65,9 @@ typedef struct {
   int32_t n_steps_traj, integrator_adj, eevpd_mode, switch_policy;
   int64_t max_steps_unadj, max_steps_total;
   int32_t full_rank_probes; /* 0: diagonal equipartition loss; P > 0: full rank, P Rademacher probes */
+  double eps_fixed;         /* 0: the adaptive step size of the unadjusted phase; > 0: this step size
+                               throughout the unadjusted phase (the fixed-step comparison of the
+                               step-size appendix); the adjusted phase starts from it as usual */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;

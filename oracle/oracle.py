@@ -45,7 +45,8 @@ class _Config(ctypes.Structure):
                 ("L_partial_factor", ctypes.c_double), ("n_steps_traj", ctypes.c_int32),
                 ("integrator_adj", ctypes.c_int32), ("eevpd_mode", ctypes.c_int32),
                 ("switch_policy", ctypes.c_int32), ("max_steps_unadj", ctypes.c_int64),
-                ("max_steps_total", ctypes.c_int64), ("full_rank_probes", ctypes.c_int32)]
+                ("max_steps_total", ctypes.c_int64), ("full_rank_probes", ctypes.c_int32),
+                ("eps_fixed", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -232,7 +233,8 @@ def fsum(v) -> float:
 # ----------------------------------------------------------------------------- ensemble
 DEFAULTS = dict(C=0.025, alpha=2.0, eps0_factor=0.01, switch_tol=0.01, window_frac=0.2, acc_tol=0.03,
                 acc_target=0.0, L_partial_factor=1.25, n_steps_traj=15, integrator_adj=0, eevpd_mode=1,
-                switch_policy=0, max_steps_unadj=1000, max_steps_total=2000, full_rank_probes=0)
+                switch_policy=0, max_steps_unadj=1000, max_steps_total=2000, full_rank_probes=0,
+                eps_fixed=0.0)
 
 _ARR = dict(x=0, u=1, g=2, logp=3, delta=4, acc=5, mean=6, var=7, m2=8, Vii=9, sigma=10, ring=11, wdelta=12)
 
@@ -247,7 +249,7 @@ class Ensemble:
         self._c = _Config(n_chains, target.d, seed, c["C"], c["alpha"], c["eps0_factor"], c["switch_tol"],
                           c["window_frac"], c["acc_tol"], c["acc_target"], c["L_partial_factor"],
                           c["n_steps_traj"], c["integrator_adj"], c["eevpd_mode"], c["switch_policy"],
-                          c["max_steps_unadj"], c["max_steps_total"], c["full_rank_probes"])
+                          c["max_steps_unadj"], c["max_steps_total"], c["full_rank_probes"], c["eps_fixed"])
         self.h = lib().orc_create(ctypes.byref(self._c), ctypes.byref(target.s))
         if not self.h:
             raise ValueError("orc_create rejected the configuration")

@@ -261,6 +261,8 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
     return why = "block_threads must be 0, 64, 128 or 256", LAPS_EINVAL;
   if (cfg->grad_workgroups < 0 || cfg->grad_workgroups > 65536)
     return why = "grad_workgroups must be in 0..65536", LAPS_EINVAL;
+  if (!(cfg->eps_fixed >= 0.0) || !isfinite(cfg->eps_fixed))
+    return why = "eps_fixed must be finite and >= 0", LAPS_EINVAL;
   if (cfg->full_rank_probes < 0 || cfg->full_rank_probes > 1024)
     return why = "full_rank_probes must be in 0..1024", LAPS_EINVAL;
   if (cfg->integrator_adj < 0 || cfg->integrator_adj > 2 || cfg->eevpd_mode < 0 || cfg->eevpd_mode > 1 ||
@@ -403,6 +405,7 @@ CtlArgs ctl_args(laps_ctx *c) {
   a.C = c->cfg.C;
   a.alpha = c->cfg.alpha;
   a.eps0_factor = c->cfg.eps0_factor;
+  a.eps_fixed = c->cfg.eps_fixed;
   a.switch_tol = c->cfg.switch_tol;
   a.acc_tol = c->cfg.acc_tol;
   a.acc_target = c->cfg.acc_target;

@@ -41,7 +41,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV
 __global__ void k_hyper_init(CtlArgs c) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   DevHyper *H = c.hyp;
-  H->eps = c.eps0_factor * sqrt((double)c.d);
+  H->eps = c.eps_fixed > 0.0 ? c.eps_fixed : c.eps0_factor * sqrt((double)c.d);
   H->L = 0.0;
   H->eevpd = H->eevpd_target = H->dtilde = H->max_delta = H->acc_mean = H->sum_var = 0.0;
   H->lo = H->hi = 0.0;
@@ -146,10 +146,13 @@ __device__ void ctl_unadj_body(const CtlArgs &c, double *sh, double &mean_sh) {
   if (bad > 0.0) H->status |= ST_NONFINITE;
   H->eevpd_target = F_bias(c.C * H->dtilde);
   const double ratio = H->eevpd_target / H->eevpd;
-  if (isfinite(ratio) && ratio > 0.0)
+  if (c.eps_fixed > 0.0) {
+    // fixed step size: the update is skipped, the diagnostics still computed
+  } else if (isfinite(ratio) && ratio > 0.0) {
     H->eps *= pow(ratio, 1.0 / 6.0);
-  else
+  } else {
     H->status |= ST_EPS_KEPT;
+  }
   H->sum_var = sV;
   H->L = c.alpha * sqrt(sV);
   H->ring_pos = (H->ring_pos + 1) % c.Tw;

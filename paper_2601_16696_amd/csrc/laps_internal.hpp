@@ -49,6 +49,7 @@ struct CtlArgs {
   const double *delta, *acc;
   int64_t N, d, ld;
   double C, alpha, eps0_factor, switch_tol, acc_tol, acc_target;
+  double eps_fixed;  // > 0: unadjusted-phase step size held at this value
   int n_traj, eevpd_mode, switch_policy, integ;
   int64_t max_unadj, max_total;
   void *sigma;

@@ -40,7 +40,8 @@ class Config(ctypes.Structure):
                 ("integrator_adj", ctypes.c_int32), ("eevpd_mode", ctypes.c_int32),
                 ("switch_policy", ctypes.c_int32), ("max_steps_unadj", ctypes.c_int64),
                 ("max_steps_total", ctypes.c_int64), ("team_lanes", ctypes.c_int32), ("full_rank_probes", ctypes.c_int32),
-                ("block_threads", ctypes.c_int32), ("grad_workgroups", ctypes.c_int32)]
+                ("block_threads", ctypes.c_int32), ("grad_workgroups", ctypes.c_int32),
+                ("eps_fixed", ctypes.c_double)]
 
 
 class TargetS(ctypes.Structure):

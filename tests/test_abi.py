@@ -213,3 +213,12 @@ def test_launch_shape_fields_validation(L):
     c.block_threads = 0
     c.grad_workgroups = -1
     assert _ws(L, c, t)[0] == L.EINVAL
+
+
+def test_eps_fixed_validation(L):
+    c, t = _cfg_target(L, kind=0, N=64, d=40)
+    c.eps_fixed = 0.5
+    assert _ws(L, c, t)[0] == L.OK
+    for bad in (-0.1, float("nan"), float("inf")):
+        c.eps_fixed = bad
+        assert _ws(L, c, t)[0] == L.EINVAL

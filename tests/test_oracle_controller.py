@@ -251,3 +251,51 @@ def test_switch_sets_preconditioner_and_integrator(orc):
         s = e.stats()
         assert s["integrator"] == integ and s["a_star"] == astar and s["phase"] == 2 and s["adapt"] == 1
         np.testing.assert_allclose(e.array("sigma") ** 2, x.var(axis=0), rtol=1e-12)
+
+
+def test_fixed_step_size_holds_eps_and_changes_nothing_else(orc):
+    """eps_fixed (the fixed-step comparison of the step-size appendix): eps
+    stays at the given value through the unadjusted phase, and the run is the
+    adaptive run with eps reset to that value before every move (L, the
+    diagnostics and the window follow the ensemble exactly as before)."""
+    d, M, E = 12, 16, 0.37
+    s2 = 10.0 ** np.linspace(-1.0, 1.0, d)
+    x0 = np.random.default_rng(5).normal(0.0, 3.0, size=(M, d))
+    fixed = orc.Ensemble(orc.Target(orc.GAUSS_DIAG, d, a=s2), M, 9, eps_fixed=E)
+    adapt = orc.Ensemble(orc.Target(orc.GAUSS_DIAG, d, a=s2), M, 9)
+    fixed.init(x0)
+    adapt.init(x0)
+    assert fixed.stats()["eps"] == E
+    for _ in range(25):
+        adapt.set_hyper(E, adapt.stats()["L"])
+        adapt.unadj_move()
+        adapt.unadj_control()
+        fixed.unadj_move()
+        fixed.unadj_control()
+        sf, sa = fixed.stats(), adapt.stats()
+        assert sf["eps"] == E and sa["eps"] != E
+        assert sf["L"] == sa["L"] and sf["eevpd"] == sa["eevpd"] and sf["dtilde"] == sa["dtilde"]
+        assert sf["status_bits"] & 2 == 0
+    assert np.array_equal(fixed.array("x"), adapt.array("x"))
+    assert np.array_equal(fixed.array("u"), adapt.array("u"))
+
+
+def test_fixed_step_size_at_eps0_matches_the_first_adaptive_step(orc):
+    """With eps_fixed = 0.01 sqrt(d) (the adaptive run's eps_0) the first step
+    of both runs is identical; the adaptive eps then moves off eps_0."""
+    d, M = 9, 12
+    x0 = np.random.default_rng(6).normal(0.0, 5.0, size=(M, d))
+    e0 = 0.01 * math.sqrt(d)
+    a = orc.Ensemble(orc.Target(orc.GAUSS_DIAG, d, a=np.ones(d)), M, 4)
+    f = orc.Ensemble(orc.Target(orc.GAUSS_DIAG, d, a=np.ones(d)), M, 4, eps_fixed=e0)
+    a.init(x0)
+    f.init(x0)
+    a.step_unadjusted(1)
+    f.step_unadjusted(1)
+    assert np.array_equal(a.array("x"), f.array("x")) and np.array_equal(a.array("delta"), f.array("delta"))
+    assert a.stats()["eps"] != e0 and f.stats()["eps"] == e0
+
+
+def test_fixed_step_size_rejects_negative(orc):
+    with pytest.raises(ValueError):
+        orc.Ensemble(orc.Target(orc.GAUSS_DIAG, 3, a=np.ones(3)), 4, 1, eps_fixed=-1.0)
