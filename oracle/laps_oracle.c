@@ -288,6 +288,29 @@ double orc_map_B(double *u, const double *gt, int64_t d, double h) {
   return (double)(d - 1) * log1p(Dm1);
 }
 
+/* Underdamped Langevin variant (appendix "Ablation studies", dynamics
+ * paragraph: the microcanonical velocity replaced by the usual Gaussian one).
+ * Reading: the velocity has covariance I/d, i.e. mass d and kinetic energy
+ * K(u) = (d/2)|u|^2, so that |u| ~ 1 as on the sphere and eps, L and the
+ * controllers keep their meaning.
+ * O: the exact Ornstein-Uhlenbeck step u <- c1 u + c2 Z, Z = xi/sqrt(d) ~ N(0, I/d),
+ *    with the same c1 = e^{-h/L}, c2 = sqrt(1 - c1^2); nothing is normalised.
+ * B: Hamilton's equation du/dt = g/d, exact for fixed g: u <- u + (h/d) g, and the
+ *    change K(u') - K(u) = h g.u + h^2 |g|^2 / (2d), written out so that it does
+ *    not cancel. */
+void orc_map_O_lang(double *u, const double *xi, int64_t d, double h, double L) {
+  const double c1 = exp(-h / L);
+  const double c2 = sqrt(-expm1(-2.0 * h / L));
+  const double sd = sqrt((double)d);
+  for (int64_t i = 0; i < d; ++i) u[i] = c1 * u[i] + c2 * xi[i] / sd;
+}
+
+double orc_map_B_lang(double *u, const double *gt, int64_t d, double h) {
+  const double gu = dot(gt, u, d), gg = dot(gt, gt, d);
+  for (int64_t i = 0; i < d; ++i) u[i] += h / (double)d * gt[i];
+  return h * gu + 0.5 * h * h * gg / (double)d;
+}
+
 /* Position update x <- x + h u; with a diagonal preconditioner sigma the
  * position moves by h sigma*u (R9). */
 void orc_map_A(double *x, const double *u, const double *sigma, int64_t d, double h) {
@@ -338,6 +361,7 @@ static double *alloc0(int64_t n) { return (double *)calloc((size_t)(n > 0 ? n : 
 orc_ctx *orc_create(const orc_config *cfg, const orc_target *tg) {
   if (cfg->d < 2 || cfg->n_chains < 2 || tg->d != cfg->d) return NULL;
   if (!(cfg->eps_fixed >= 0.0) || !isfinite(cfg->eps_fixed)) return NULL;
+  if (cfg->dynamics != 0 && cfg->dynamics != 1) return NULL;
   orc_ctx *c = (orc_ctx *)calloc(1, sizeof(orc_ctx));
   c->cfg = *cfg;
   c->tg = *tg;
@@ -485,7 +509,7 @@ static double integrate(orc_ctx *c, double *x, double *u, double *g, double *lp,
   for (int k = 0; k < K; ++k) {
     /* B with the gradient in the sampler's coordinates (sigma*g when preconditioned) */
     for (int64_t i = 0; i < d; ++i) c->tmp[i] = sigma ? sigma[i] * g[i] : g[i];
-    dE += orc_map_B(u, c->tmp, d, b[k] * eps);
+    dE += c->cfg.dynamics ? orc_map_B_lang(u, c->tmp, d, b[k] * eps) : orc_map_B(u, c->tmp, d, b[k] * eps);
     if (k == K - 1) break;
     orc_map_A(x, u, sigma, d, a[k] * eps);
     const double lnew = orc_logp_grad(&c->tg, x, g);
@@ -493,6 +517,12 @@ static double integrate(orc_ctx *c, double *x, double *u, double *g, double *lp,
     *lp = lnew;
   }
   return dE;
+}
+
+/* The partial refresh of the configured dynamics with the normals in c->z. */
+static void refresh(orc_ctx *c, double *u, double h, double L) {
+  if (c->cfg.dynamics) orc_map_O_lang(u, c->z, c->d, h, L);
+  else orc_map_O(u, c->z, c->d, h, L);
 }
 
 /* One unadjusted MCLMC step (eq. discrete update): O_{eps/2} Phi_eps O_{eps/2}
@@ -504,10 +534,10 @@ void orc_unadj_move(orc_ctx *c) {
   for (int64_t m = 0; m < N; ++m) {
     double *x = c->x + m * d, *u = c->u + m * d, *g = c->g + m * d;
     orc_normals(c->cfg.seed, (uint64_t)m, (uint64_t)c->t, ORC_TAG_O_FIRST, 0, d, c->z);
-    orc_map_O(u, c->z, d, h, c->L);
+    refresh(c, u, h, c->L);
     const double dE = integrate(c, x, u, g, &c->logp[m], 0, c->eps, NULL);
     orc_normals(c->cfg.seed, (uint64_t)m, (uint64_t)c->t, ORC_TAG_O_SECOND, 0, d, c->z);
-    orc_map_O(u, c->z, d, h, c->L);
+    refresh(c, u, h, c->L);
     c->delta[m] = dE;
   }
 }
@@ -633,15 +663,16 @@ void orc_mams_move(orc_ctx *c) {
     memcpy(c->g0, g, sizeof(double) * d);
     const double l0 = c->logp[m];
     orc_normals(c->cfg.seed, (uint64_t)m, (uint64_t)c->t, ORC_TAG_FULL_REFRESH, 0, d, c->z);
-    const double zn = sqrt(dot(c->z, c->z, d));
+    /* full refresh: uniform on the sphere, or N(0, I/d) for the Langevin variant */
+    const double zn = c->cfg.dynamics ? sqrt((double)d) : sqrt(dot(c->z, c->z, d));
     for (int64_t i = 0; i < d; ++i) u[i] = c->z[i] / zn;
     double D = 0.0;
     for (int j = 0; j < ns; ++j) {
       orc_normals(c->cfg.seed, (uint64_t)m, (uint64_t)c->t, ORC_TAG_O_FIRST, (uint32_t)j, d, c->z);
-      orc_map_O(u, c->z, d, h, Lp);
+      refresh(c, u, h, Lp);
       D += integrate(c, x, u, g, &c->logp[m], c->integ, eps, c->sigma);
       orc_normals(c->cfg.seed, (uint64_t)m, (uint64_t)c->t, ORC_TAG_O_SECOND, (uint32_t)j, d, c->z);
-      orc_map_O(u, c->z, d, h, Lp);
+      refresh(c, u, h, Lp);
     }
     c->delta[m] = D;
     const double w = exp(-D);

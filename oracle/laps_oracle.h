@@ -53,6 +53,11 @@ double orc_logp_grad(const orc_target *tg, const double *x, double *g);
 void orc_map_O(double *u, const double *z, int64_t d, double h, double L);
 double orc_map_B(double *u, const double *gt, int64_t d, double h);
 void orc_map_A(double *x, const double *u, const double *sigma, int64_t d, double h);
+/* Underdamped Langevin variant: velocity u ~ N(0, I/d) (mass d, so |u| ~ 1 and
+ * eps, L keep the units of the microcanonical dynamics), kinetic energy
+ * K(u) = (d/2)|u|^2. */
+void orc_map_O_lang(double *u, const double *xi, int64_t d, double h, double L);
+double orc_map_B_lang(double *u, const double *gt, int64_t d, double h);
 
 /* coefficient sets: 0 = LF, 1 = MN2, 2 = MN4 */
 int orc_integrator_coeffs(int which, double *b, double *a, int *K);
@@ -68,6 +73,8 @@ typedef struct {
   double eps_fixed;         /* 0: the adaptive step size of the unadjusted phase; > 0: this step size
                                throughout the unadjusted phase (the fixed-step comparison of the
                                step-size appendix); the adjusted phase starts from it as usual */
+  int32_t dynamics;         /* 0: microcanonical velocity (the method); 1: underdamped Langevin with a
+                               Gaussian velocity (the dynamics ablation of appendix "Ablation studies") */
 } orc_config;
 
 typedef struct orc_ctx orc_ctx;

@@ -46,7 +46,7 @@ class _Config(ctypes.Structure):
                 ("integrator_adj", ctypes.c_int32), ("eevpd_mode", ctypes.c_int32),
                 ("switch_policy", ctypes.c_int32), ("max_steps_unadj", ctypes.c_int64),
                 ("max_steps_total", ctypes.c_int64), ("full_rank_probes", ctypes.c_int32),
-                ("eps_fixed", ctypes.c_double)]
+                ("eps_fixed", ctypes.c_double), ("dynamics", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -77,6 +77,8 @@ def lib():
             "orc_logp_grad": (D, [P, P, P]),
             "orc_map_O": (None, [P, P, I64, D, D]),
             "orc_map_B": (D, [P, P, I64, D]),
+            "orc_map_O_lang": (None, [P, P, I64, D, D]),
+            "orc_map_B_lang": (D, [P, P, I64, D]),
             "orc_map_A": (None, [P, P, P, I64, D]),
             "orc_integrator_coeffs": (I32, [I32, P, P, P]),
             "orc_create": (P, [P, P]),
@@ -203,6 +205,20 @@ def map_B(u, gt, h) -> tuple[np.ndarray, float]:
     return u, dk
 
 
+def map_O_lang(u, xi, h, L) -> np.ndarray:
+    u = _f64(u).copy()
+    xi = _f64(xi)
+    lib().orc_map_O_lang(_p(u), _p(xi), u.size, h, L)
+    return u
+
+
+def map_B_lang(u, gt, h) -> tuple[np.ndarray, float]:
+    u = _f64(u).copy()
+    gt = _f64(gt)
+    dk = lib().orc_map_B_lang(_p(u), _p(gt), u.size, h)
+    return u, dk
+
+
 def map_A(x, u, h, sigma=None) -> np.ndarray:
     x = _f64(x).copy()
     u = _f64(u)
@@ -234,7 +250,7 @@ def fsum(v) -> float:
 DEFAULTS = dict(C=0.025, alpha=2.0, eps0_factor=0.01, switch_tol=0.01, window_frac=0.2, acc_tol=0.03,
                 acc_target=0.0, L_partial_factor=1.25, n_steps_traj=15, integrator_adj=0, eevpd_mode=1,
                 switch_policy=0, max_steps_unadj=1000, max_steps_total=2000, full_rank_probes=0,
-                eps_fixed=0.0)
+                eps_fixed=0.0, dynamics=0)
 
 _ARR = dict(x=0, u=1, g=2, logp=3, delta=4, acc=5, mean=6, var=7, m2=8, Vii=9, sigma=10, ring=11, wdelta=12)
 
@@ -249,7 +265,7 @@ class Ensemble:
         self._c = _Config(n_chains, target.d, seed, c["C"], c["alpha"], c["eps0_factor"], c["switch_tol"],
                           c["window_frac"], c["acc_tol"], c["acc_target"], c["L_partial_factor"],
                           c["n_steps_traj"], c["integrator_adj"], c["eevpd_mode"], c["switch_policy"],
-                          c["max_steps_unadj"], c["max_steps_total"], c["full_rank_probes"], c["eps_fixed"])
+                          c["max_steps_unadj"], c["max_steps_total"], c["full_rank_probes"], c["eps_fixed"], c["dynamics"])
         self.h = lib().orc_create(ctypes.byref(self._c), ctypes.byref(target.s))
         if not self.h:
             raise ValueError("orc_create rejected the configuration")
