@@ -162,6 +162,11 @@ typedef struct {
                                > 0: this step size throughout the unadjusted phase, all else unchanged
                                (the fixed-step comparison of the step-size appendix); the adjusted
                                phase starts from it and bisects as usual */
+  int32_t dynamics;         /* 0: the microcanonical velocity (the paper's method); 1: underdamped
+                               Langevin (the dynamics ablation of appendix "Ablation studies"): velocity
+                               u ~ N(0, I/d), kinetic energy (d/2)|u|^2, Ornstein-Uhlenbeck refresh
+                               u <- c1 u + sqrt(1 - c1^2) Z/sqrt(d) and kick u <- u + (h/d) g; eps, L,
+                               the controllers and MH are unchanged */
 } laps_config;
 
 /* Snapshot of the device-resident hyperparameters and diagnostics.

@@ -1,6 +1,7 @@
-"""Ablation sweeps of the hyperparameters (appendix "Ablation studies" and the
-step-size comparison of the appendix on the adaptive step size) on targets with
-closed-form second moments, run through the library's sampler.
+"""Ablation sweeps of the hyperparameters and of the dynamics (appendix
+"Ablation studies" and the step-size comparison of the appendix on the adaptive
+step size) on targets with closed-form second moments, run through the
+library's sampler.
 
 The paper's metric is the number of gradient calls per chain until the squared
 bias of the second moments first drops below 0.01 (b^2_max; b^2_avg for the
@@ -154,6 +155,9 @@ def sweep(target: str = "gauss", prec="f64", log=None) -> dict:
                           **run(f"eps={f}x", unadjusted_only=True, max_total=2000, stop_at_hit=False,
                                 eps_fixed=f * eps_ref)))
     out["fixed_eps"] = _relative(fixed)
+    # microcanonical vs underdamped Langevin dynamics, the rest of the scheme unchanged
+    out["dynamics"] = _relative([dict(dynamics=name, **run(f"dynamics={name}", dynamics=v))
+                                 for v, name in ((0, "microcanonical"), (1, "langevin"))])
     return out
 
 

@@ -263,6 +263,7 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
     return why = "grad_workgroups must be in 0..65536", LAPS_EINVAL;
   if (!(cfg->eps_fixed >= 0.0) || !isfinite(cfg->eps_fixed))
     return why = "eps_fixed must be finite and >= 0", LAPS_EINVAL;
+  if (cfg->dynamics != 0 && cfg->dynamics != 1) return why = "dynamics must be 0 or 1", LAPS_EINVAL;
   if (cfg->full_rank_probes < 0 || cfg->full_rank_probes > 1024)
     return why = "full_rank_probes must be in 0..1024", LAPS_EINVAL;
   if (cfg->integrator_adj < 0 || cfg->integrator_adj > 2 || cfg->eevpd_mode < 0 || cfg->eevpd_mode > 1 ||
@@ -338,6 +339,7 @@ LocalArgs local_args(laps_ctx *c) {
   a.n_traj = c->cfg.n_steps_traj;
   a.Lp_factor = c->cfg.L_partial_factor;
   a.cache = 0;
+  a.dyn = c->cfg.dynamics;
   return a;
 }
 
@@ -379,6 +381,7 @@ LogregArgs logreg_args(laps_ctx *c, int gate) {
   a.Lp_factor = c->cfg.L_partial_factor;
   a.gate = gate;
   a.integ = c->integ;
+  a.dyn = c->cfg.dynamics;
   return a;
 }
 

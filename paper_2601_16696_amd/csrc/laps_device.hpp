@@ -263,6 +263,35 @@ __device__ __forceinline__ BMap b_map_t(double gg, double gu, double h, double d
   return sizeof(Real) == 8 ? b_map(gg, gu, h, dm1) : b_map_f(gg, gu, h, dm1);
 }
 
+// Underdamped Langevin variant (the dynamics ablation of appendix "Ablation
+// studies"): Gaussian velocity with covariance I/d (mass d, so |u| ~ 1 and eps,
+// L keep their units).  The kick is exact for fixed g, u' = u + (h/d) g~, with
+// kinetic change (d/2)(|u'|^2 - |u|^2) = h g~.u + h^2 |g~|^2 / (2d); the refresh
+// is the microcanonical one without the renormalisation.  dyn selects the
+// dynamics for the whole launch (a uniform branch).
+template <class Real>
+__device__ __forceinline__ BMap b_map_dyn(int dyn, double gg, double gu, double h, double dm1) {
+  if (dyn) {
+    const double dd = dm1 + 1.0;
+    BMap r;
+    r.A = 1.0;
+    r.Bg = h / dd;
+    r.dK = h * gu + 0.5 * h * h * gg / dd;
+    return r;
+  }
+  return b_map_t<Real>(gg, gu, h, dm1);
+}
+
+// Scale applied after a partial refresh with squared norm ww: back onto the
+// unit sphere (microcanonical), none (Langevin).
+__device__ __forceinline__ double refresh_scale(int dyn, double ww) { return dyn ? 1.0 : 1.0 / sqrt(ww); }
+
+// Scale of a full refresh of d standard normals with squared norm zz: uniform
+// on the sphere (microcanonical) or N(0, I/d) (Langevin).
+__device__ __forceinline__ double full_refresh_scale(int dyn, double zz, int64_t d) {
+  return dyn ? 1.0 / sqrt((double)d) : 1.0 / sqrt(zz);
+}
+
 // Integrator coefficient sets (Table "Integrators"): symmetric B A B ... B,
 // the coefficients not printed follow from symmetry and normalisation.
 struct Coeffs {

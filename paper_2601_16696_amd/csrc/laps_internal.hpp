@@ -31,6 +31,7 @@ struct LocalArgs {
   int n_traj;
   double Lp_factor;
   int cache;               // store g and log p (1) or recompute them (0)
+  int dyn;                 // 0 microcanonical velocity, 1 underdamped Langevin
   int stats;               // accumulate per-dim sums in the step kernel (1) or leave them to k_stats (0)
   double *logp_out;        // target eval: log p output
   void *g_out;             // target eval: gradient output (or null)
@@ -116,6 +117,7 @@ struct LogregArgs {
   int64_t n, N, d, ld;
   int S, NB, KC, bps;      // row splits, 32-row blocks, 32-wide k chunks, blocks per split
   int T, tpw;              // team shape of the update kernels
+  int dyn;                 // 0 microcanonical velocity, 1 underdamped Langevin
   uint64_t seed;
   int64_t max_total;
   int n_traj;

@@ -534,8 +534,8 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
       oct_fence();
     }
     team_sum<4>(v4, T, tm.red, tm.slot);
-    const double inw = 1.0 / sqrt(v4[1]);
-    const BMap b1 = b_map_t<Real>(v4[3], v4[2] * inw, h, dm1);
+    const double inw = refresh_scale(a.dyn, v4[1]);
+    const BMap b1 = b_map_dyn<Real>(a.dyn, v4[3], v4[2] * inw, h, dm1);
     const Real A1 = (Real)(b1.A * inw), B1 = (Real)b1.Bg;
 #pragma unroll
     for (int q = 0; q < Q; ++q)
@@ -558,7 +558,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
       v3[2] += widen(p2);
     }
     team_sum<3>(v3, T, tm.red, tm.slot);
-    const BMap b2 = b_map_t<Real>(v3[1], v3[2], h, dm1);
+    const BMap b2 = b_map_dyn<Real>(a.dyn, v3[1], v3[2], h, dm1);
     const Real A2 = (Real)b2.A, B2 = (Real)b2.Bg;
     double v1[1] = {0.0};
 #pragma unroll
@@ -576,7 +576,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
       oct_fence();
     }
     team_sum<1>(v1, T, tm.red, tm.slot);
-    const Real in2 = (Real)(1.0 / sqrt(v1[0]));
+    const Real in2 = (Real)refresh_scale(a.dyn, v1[0]);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -650,7 +650,7 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
     team_sum<2>(v2, T, tm.red, tm.slot);
     lp = v2[0];
     {
-      const Real iz = (Real)(1.0 / sqrt(v2[1]));
+      const Real iz = (Real)full_refresh_scale(a.dyn, v2[1], d);
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -678,8 +678,8 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
         oct_fence();
       }
       team_sum<3>(v3, T, tm.red, tm.slot);
-      const double inw = 1.0 / sqrt(v3[0]);
-      BMap b = b_map_t<Real>(v3[2], v3[1] * inw, C.b[0] * eps, dm1);
+      const double inw = refresh_scale(a.dyn, v3[0]);
+      BMap b = b_map_dyn<Real>(a.dyn, v3[2], v3[1] * inw, C.b[0] * eps, dm1);
       D += b.dK;
       {
         const Real Ab = (Real)(b.A * inw), Bb = (Real)b.Bg;
@@ -719,7 +719,7 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
         team_sum<3>(w3, T, tm.red, tm.slot);
         D += lp - w3[0];
         lp = w3[0];
-        b = b_map_t<Real>(w3[1], w3[2], kCoefB[INTEG][k + 1] * eps, dm1);
+        b = b_map_dyn<Real>(a.dyn, w3[1], w3[2], kCoefB[INTEG][k + 1] * eps, dm1);
         D += b.dK;
         const Real Ab = (Real)b.A, Bb = (Real)b.Bg;
 #pragma unroll
@@ -743,7 +743,7 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
         oct_fence();
       }
       team_sum<1>(v1, T, tm.red, tm.slot);
-      const Real in2 = (Real)(1.0 / sqrt(v1[0]));
+      const Real in2 = (Real)refresh_scale(a.dyn, v1[0]);
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll

@@ -779,7 +779,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
       }
       team_sum<3>(v, T, red, slot);
       const double l1 = lps - (a.prior ? 0.5 * v[0] : 0.0);
-      const BMap b2 = b_map_t<Real>(v[1], v[2], h, dm1);
+      const BMap b2 = b_map_dyn<Real>(a.dyn, v[1], v[2], h, dm1);
       lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, 0, z);
       double w1[1] = {0.0};
 #pragma unroll
@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
         w1[0] += (double)w * (double)w;
       }
       team_sum<1>(w1, T, red, slot);
-      const Real inw = (Real)(1.0 / sqrt(w1[0]));
+      const Real inw = (Real)refresh_scale(a.dyn, w1[0]);
 #pragma unroll
       for (int i = 0; i < 8; ++i) u[0][i] *= inw;
       if (act) {
@@ -822,8 +822,8 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
       v[2] += (double)g[0][i] * (double)g[0][i];
     }
     team_sum<3>(v, T, red, slot);
-    const double inw = 1.0 / sqrt(v[0]);
-    const BMap b1 = b_map_t<Real>(v[2], v[1] * inw, h, dm1);
+    const double inw = refresh_scale(a.dyn, v[0]);
+    const BMap b1 = b_map_dyn<Real>(a.dyn, v[2], v[1] * inw, h, dm1);
     const Real A1 = (Real)(b1.A * inw), B1 = (Real)b1.Bg, epsR = (Real)eps;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -862,8 +862,8 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
       v[2] += (double)gt * (double)gt;
     }
     team_sum<3>(v, T, red, slot);
-    const double inw = 1.0 / sqrt(v[0]);
-    const BMap b = b_map_t<Real>(v[2], v[1] * inw, a.cb0 * eps, dm1);
+    const double inw = refresh_scale(a.dyn, v[0]);
+    const BMap b = b_map_dyn<Real>(a.dyn, v[2], v[1] * inw, a.cb0 * eps, dm1);
     D += b.dK;
     const Real Ab = (Real)(b.A * inw), Bb = (Real)b.Bg, ha = (Real)(a.ca0 * eps);
 #pragma unroll
@@ -885,7 +885,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) v1[0] += (double)z[0][i] * (double)z[0][i];
     team_sum<1>(v1, T, red, slot);
-    const Real iz = (Real)(1.0 / sqrt(v1[0]));
+    const Real iz = (Real)full_refresh_scale(a.dyn, v1[0], d);
 #pragma unroll
     for (int i = 0; i < 8; ++i) u[0][i] = z[0][i] * iz;
     step_start(0);
@@ -919,7 +919,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   lprev = lnew;
   const int k = a.k, j = a.j;
   {
-    const BMap b = b_map_t<Real>(v[1], v[2], a.cbk * eps, dm1);
+    const BMap b = b_map_dyn<Real>(a.dyn, v[1], v[2], a.cbk * eps, dm1);
     D += b.dK;
     const Real Ab = (Real)b.A, Bb = (Real)b.Bg;
 #pragma unroll
@@ -939,7 +939,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
       w1[0] += (double)w * (double)w;
     }
     team_sum<1>(w1, T, red, slot);
-    const Real inw = (Real)(1.0 / sqrt(w1[0]));
+    const Real inw = (Real)refresh_scale(a.dyn, w1[0]);
 #pragma unroll
     for (int i = 0; i < 8; ++i) u[0][i] *= inw;
     if (j + 1 < a.n_traj) {

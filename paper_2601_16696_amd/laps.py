@@ -41,7 +41,7 @@ class Config(ctypes.Structure):
                 ("switch_policy", ctypes.c_int32), ("max_steps_unadj", ctypes.c_int64),
                 ("max_steps_total", ctypes.c_int64), ("team_lanes", ctypes.c_int32), ("full_rank_probes", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("grad_workgroups", ctypes.c_int32),
-                ("eps_fixed", ctypes.c_double)]
+                ("eps_fixed", ctypes.c_double), ("dynamics", ctypes.c_int32)]
 
 
 class TargetS(ctypes.Structure):

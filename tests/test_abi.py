@@ -222,3 +222,12 @@ def test_eps_fixed_validation(L):
     for bad in (-0.1, float("nan"), float("inf")):
         c.eps_fixed = bad
         assert _ws(L, c, t)[0] == L.EINVAL
+
+
+def test_dynamics_validation(L):
+    c, t = _cfg_target(L, kind=0, N=64, d=40)
+    for v in (0, 1):
+        c.dynamics = v
+        assert _ws(L, c, t)[0] == L.OK
+    c.dynamics = 2
+    assert _ws(L, c, t)[0] == L.EINVAL
