@@ -89,7 +89,7 @@ __device__ __forceinline__ void chain_sums(const double *a, int64_t N, double sh
   bad = v2[1];
 }
 
-// The unadjusted-phase controller (one workgroup of 1024 threads, after the
+// The unadjusted-phase controller (one workgroup of 128 or 256 threads, after the
 // statistics pass of the step has written its block scalars).
 __device__ void ctl_unadj_body(const CtlArgs &c, double *sh, double &mean_sh) {
   DevHyper *H = c.hyp;
@@ -169,8 +169,8 @@ __device__ void ctl_unadj_body(const CtlArgs &c, double *sh, double &mean_sh) {
   if ((c.switch_policy == 0 && H->switch_ready) || H->t >= c.max_unadj) H->phase = PH_SWITCH_PENDING;
 }
 
-// DIMS dimensions per 1024-thread block (8 up to d = 1024, else 32): row
-// group rg (0 .. 1024/DIMS - 1) of dimension column dl sums partial rows rg,
+// DIMS dimensions per THREADS-thread block (8 up to d = 1024, else 32): row
+// group rg (0 .. THREADS/DIMS - 1) of dimension column dl sums partial rows rg,
 // rg + groups, ...; the group sums are combined first inside each wavefront
 // by xor butterflies over the group bits, then over the wavefronts in order
 // through LDS, so the result does not depend on timing.  The moving window is
@@ -197,9 +197,9 @@ __device__ __forceinline__ void fin_combine(double (&v)[4], double *sh, int dl, 
   __syncthreads();
 }
 
-template <int DIMS>
-__global__ void __launch_bounds__(1024) k_finalize(CtlArgs c, int mode) {
-  constexpr int kFinDims = DIMS, kFinGroups = 1024 / DIMS;
+template <int DIMS, int THREADS>
+__global__ void __launch_bounds__(THREADS) k_finalize(CtlArgs c, int mode) {
+  constexpr int kFinDims = DIMS, kFinGroups = THREADS / DIMS;
   const DevHyper *H = c.hyp;
   if (mode == FIN_UNADJ && H->phase != PH_UNADJ) return;
   __shared__ double sh[16 * 4 * kFinDims];
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) k_ctl_init(CtlArgs c) {
   H->L = c.alpha * sqrt(sv);
 }
 
-__global__ void __launch_bounds__(1024) k_ctl_unadj(CtlArgs c) {
+__global__ void __launch_bounds__(256) k_ctl_unadj(CtlArgs c) {
   __shared__ double sh[16 * 8];
   __shared__ double mean_sh;
   ctl_unadj_body(c, sh, mean_sh);
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(256) k_switch(CtlArgs c) {
   }
 }
 
-__global__ void __launch_bounds__(1024) k_ctl_adj(CtlArgs c) {
+__global__ void __launch_bounds__(256) k_ctl_adj(CtlArgs c) {
   DevHyper *H = c.hyp;
   if (H->phase != PH_ADJ || H->t >= c.max_total) return;
   __shared__ double sh[16 * 4];
@@ -511,16 +511,23 @@ hipError_t launch_probes(const CtlArgs &c, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Launch shapes of the scalar controllers and the statistics finalisation,
+// from a sweep on the MI355X: one workgroup of 128 threads (N <= 2048) or 256
+// for the controllers (against 1024: 9.3 -> 4.8 us at N = 1024, 9.6 -> 6.5 us
+// at N = 4096), 512 threads per finalisation workgroup (9.5 -> 7.6 us at
+// d = 100 and G = 64 partial rows, 10.8 -> 10.0 us at G = 256).
+static unsigned ctl_threads(int64_t N) { return N <= 2048 ? 128u : 256u; }
+
 hipError_t launch_ctl_unadj(const CtlArgs &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_unadj, dim3(1), dim3(1024), 0, s, c);
+  hipLaunchKernelGGL(k_ctl_unadj, dim3(1), dim3(ctl_threads(c.N)), 0, s, c);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const CtlArgs &c, int mode, hipStream_t s) {
   if (fin_dims(c.d) == 8)
-    hipLaunchKernelGGL(k_finalize<8>, dim3(c.nb), dim3(1024), 0, s, c, mode);
+    hipLaunchKernelGGL((k_finalize<8, 512>), dim3(c.nb), dim3(512), 0, s, c, mode);
   else
-    hipLaunchKernelGGL(k_finalize<32>, dim3(c.nb), dim3(1024), 0, s, c, mode);
+    hipLaunchKernelGGL((k_finalize<32, 512>), dim3(c.nb), dim3(512), 0, s, c, mode);
   return hipGetLastError();
 }
 hipError_t launch_ctl_init(const CtlArgs &c, hipStream_t s) {
@@ -532,7 +539,7 @@ hipError_t launch_switch(const CtlArgs &c, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_ctl_adj(const CtlArgs &c, hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_adj, dim3(1), dim3(1024), 0, s, c);
+  hipLaunchKernelGGL(k_ctl_adj, dim3(1), dim3(ctl_threads(c.N)), 0, s, c);
   return hipGetLastError();
 }
 
