@@ -154,8 +154,9 @@ typedef struct {
                                P in 1..1024: the full-rank loss by Hutchinson's estimator with P
                                Rademacher probes drawn from the Philox stream each unadjusted
                                step (the paper uses 100) */
-  int32_t block_threads;    /* per-chain kernels with teams of <= 64 lanes: 0 = automatic (256),
-                               or 64, 128, 256 threads per workgroup */
+  int32_t block_threads;    /* per-chain kernels with teams of <= 64 lanes, and the per-chain update
+                               kernels of logistic regression, caller-supplied and dense targets:
+                               0 = automatic (256), or 64, 128, 256 threads per workgroup */
   int32_t grad_workgroups;  /* logistic regression: 0 = automatic, else the number of workgroups a
                                gradient launch aims for (sets the row splits) */
   double eps_fixed;         /* 0: the adaptive step size of section "Step size" (the paper's method);

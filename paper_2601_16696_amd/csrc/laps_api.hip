@@ -163,8 +163,8 @@ bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
     while (T < octs) T <<= 1;
     s.T = T;
     s.Q = 1;
-    s.block = 256;
-    s.tpw = 256 / T;
+    s.block = cfg->block_threads > 0 ? cfg->block_threads : 256;  // 64, 128 or 256 >= T
+    s.tpw = s.block / T;
     s.G = (int)((cfg->n_chains + s.tpw - 1) / s.tpw);
     s.grid_full = s.G;
     s.split = false;
@@ -488,7 +488,7 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     a.ca0 = C.a[0];
     a.cbk = k + 1 < 6 ? C.b[k + 1] : 0.0;
     a.cak = k + 1 < 5 ? C.a[k + 1] : 0.0;
-    return launch_logreg_update(prec, a, c->G, c->shmem, c->stream);
+    return launch_logreg_update(prec, a, c->G, c->block, c->shmem, c->stream);
   };
   const bool cb = c->tg.kind == LAPS_CALLBACK;
   int cb_rc = 0;

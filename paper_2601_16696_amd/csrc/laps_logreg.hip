@@ -1046,11 +1046,11 @@ hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, size_t shmem, hipStream_t s) {
+hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, int block, size_t shmem, hipStream_t s) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_lr_update<double>, dim3(grid), dim3(256), shmem, s, a);
+    hipLaunchKernelGGL(k_lr_update<double>, dim3(grid), dim3(block), shmem, s, a);
   else
-    hipLaunchKernelGGL(k_lr_update<float>, dim3(grid), dim3(256), shmem, s, a);
+    hipLaunchKernelGGL(k_lr_update<float>, dim3(grid), dim3(block), shmem, s, a);
   return hipGetLastError();
 }
 

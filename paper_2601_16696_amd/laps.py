@@ -462,8 +462,8 @@ def log_density(target: "Target", x):
 
 def _shape_candidates(w: dict, prec) -> list:
     """Launch shapes worth timing for a workload: team widths and workgroup
-    sizes of the per-chain kernels, or gradient workgroup counts for logistic
-    regression (others have one shape)."""
+    sizes of the per-chain kernels, or gradient workgroup counts and update
+    workgroup sizes for logistic regression (others have one shape)."""
     kind = KINDS[w["kind"]]
     if kind in (GAUSS_DIAG, STOCHVOL, PHI4):
         out = [dict(team_lanes=0, block_threads=0)]
@@ -472,7 +472,7 @@ def _shape_candidates(w: dict, prec) -> list:
                 out.append(dict(team_lanes=T, block_threads=b))
         return out
     if kind == LOGREG:
-        return [dict(grad_workgroups=g) for g in (0, 256, 512, 1024)]
+        return [dict(grad_workgroups=g, block_threads=b) for g in (0, 256, 512, 1024) for b in (0, 64, 128)]
     return [dict()]
 
 

@@ -94,9 +94,10 @@ def test_gradient_at_init_bf16_error_bounds(gpu, orc, shape):
         assert np.all(np.abs(g[m] - g_ref) <= bound_g), (m, np.max(np.abs(g[m] - g_ref) / bound_g))
 
 
-def test_unadjusted_and_adjusted_f64(gpu, orc):
+@pytest.mark.parametrize("block_threads", [0, 64, 128])
+def test_unadjusted_and_adjusted_f64(gpu, orc, block_threads):
     w = _w(100, 300, 37)
-    cfg = dict(switch_policy=1, max_steps_unadj=15, max_steps_total=400)
+    cfg = dict(switch_policy=1, max_steps_unadj=15, max_steps_total=400, block_threads=block_threads)
     o = _oracle(orc, w, **cfg)
     s = gpu.Sampler(w, "f64", **cfg)
     for k in range(15):
