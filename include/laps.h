@@ -235,6 +235,16 @@ laps_status laps_ensemble_stats(laps_ctx *ctx, laps_stats *out_host, double *per
 laps_status laps_target_eval(const laps_target *target, int32_t prec, const void *x_dev, void *logp_dev,
                              void *grad_dev, int64_t n_chains, void *stream);
 
+/* log p and its gradient (the target's own adjoint kernels) at caller
+ * positions x_dev ([n_chains][ld] of the context's state type, 32-byte
+ * aligned, n_chains the context's) for any target kind, including those
+ * whose gradient needs the context's scratch (logistic regression, the dense
+ * Gaussian, callbacks): logp_dev [n_chains] doubles, grad_dev [n_chains][ld]
+ * in the state type (may be NULL).  Enqueued on the context's stream between
+ * steps; the sampler's state is not touched, its split scratch is reused.
+ * Used by the autograd wrapper. */
+laps_status laps_eval(laps_ctx *ctx, const void *x_dev, void *logp_dev, void *grad_dev);
+
 /* The sampler's random-number contract, exposed for reproduction and tests.
  * Philox4x64-10 (Salmon et al., SC'11) under key (seed, 0):
  *   laps_philox_words: ctr_dev [n][4] uint64 counters -> out_dev [n][4]

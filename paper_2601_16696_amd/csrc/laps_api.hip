@@ -765,6 +765,37 @@ extern "C" laps_status laps_target_eval(const laps_target *tg, int32_t prec, con
   return LAPS_EUNSUPPORTED;
 }
 
+extern "C" laps_status laps_eval(laps_ctx *c, const void *x_dev, void *logp_dev, void *grad_dev) {
+  if (!c || !x_dev || !logp_dev) return LAPS_EINVAL;
+  if (((uintptr_t)x_dev & 31) || (grad_dev && ((uintptr_t)grad_dev & 31))) return LAPS_EINVAL;
+  if (is_local(c->tg.kind))
+    return laps_target_eval(&c->tg, c->cfg.prec, x_dev, logp_dev, grad_dev, c->cfg.n_chains, c->stream);
+  const int prec = c->cfg.prec;
+  LogregArgs a = logreg_args(c, 0);
+  a.x = const_cast<void *>(x_dev);
+  hipError_t e = hipSuccess;
+  if (c->tg.kind == LAPS_GAUSS_DENSE) {
+    e = launch_dense_grad(prec == LAPS_F64 ? 0 : 1, a, c->stream);
+  } else if (c->tg.kind == LAPS_CALLBACK) {
+    const LrOffsets off = logreg_layout(c->dbl ? 0 : 1, 0, a.d, a.N, a.ld, 1);
+    const int rc = c->tg.cb(c->tg.cb_user, x_dev, a.scratch + off.Gp, reinterpret_cast<double *>(a.scratch + off.lp),
+                            a.N, a.d, a.ld, c->stream);
+    if (rc != 0) {
+      c->err = g_last_global = "gradient callback returned " + std::to_string(rc);
+      return LAPS_EDEVICE;
+    }
+  } else {
+    e = launch_logreg_grad(prec, a, c->stream);
+  }
+  if (e == hipSuccess) {
+    a.mode = LR_EVAL;
+    a.logp_out = static_cast<double *>(logp_dev);
+    a.g_out = grad_dev;
+    e = launch_logreg_update(prec, a, c->G, c->block, c->shmem, c->stream);
+  }
+  return e == hipSuccess ? LAPS_OK : fail(c, e, "evaluation");
+}
+
 extern "C" laps_status laps_restart(laps_ctx *c, const void *x0_dev) {
   if (!c) return LAPS_EINVAL;
   if (x0_dev && ((uintptr_t)x0_dev & 31)) return LAPS_EINVAL;

@@ -129,9 +129,11 @@ struct LogregArgs {
   double cb0, ca0, cbk, cak;
   int cK;
   int prior;               // 1: add the N(0, I) prior of logistic regression to the partial sums; 0: caller's log p
+  double *logp_out;        // LR_EVAL: log p output [N]
+  void *g_out;             // LR_EVAL: gradient output [N][ld] (or null)
 };
 
-enum { LR_INIT = 0, LR_PRE = 1, LR_POST = 2, LR_MBEGIN = 3, LR_MSTEP = 4 };
+enum { LR_INIT = 0, LR_PRE = 1, LR_POST = 2, LR_MBEGIN = 3, LR_MSTEP = 4, LR_EVAL = 5 };
 
 struct LrOffsets {
   size_t Xf, Xb, yf, Gp, lp, x0, g0, sc, total;

@@ -725,6 +725,21 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   load_row<Real, 1>(X + m * ld, r, T, d, act, x);
   const int mode = a.mode;
 
+  if (mode == LR_EVAL) {
+    // log p and gradient at the caller's positions (a.x): split sums plus the prior
+    double lps;
+    lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
+    double v[1] = {0.0};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[0] += (double)x[0][i] * (double)x[0][i];
+    team_sum<1>(v, T, red, slot);
+    if (act) {
+      if (a.g_out) store_row<Real, 1>(static_cast<Real *>(a.g_out) + m * ld, r, T, d, g);
+      if (r == 0) a.logp_out[m] = lps - (a.prior ? 0.5 * v[0] : 0.0);
+    }
+    return;
+  }
+
   if (mode == LR_INIT || mode == LR_POST) {
     double S[4][1][8] = {};
     // every global load of this stage is issued before the first dependent use

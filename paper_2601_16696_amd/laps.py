@@ -62,7 +62,7 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["laps_config_default", "laps_row_stride", "laps_workspace_size", "laps_init", "laps_step_unadjusted",
-           "laps_step_adjusted", "laps_ensemble_stats", "laps_target_eval", "laps_philox_words",
+           "laps_step_adjusted", "laps_ensemble_stats", "laps_target_eval", "laps_eval", "laps_philox_words",
            "laps_philox_normals", "laps_time_gradient", "laps_time_kernel", "laps_kernel_log",
            "laps_kernel_log_read", "laps_restart", "laps_graph_create",
            "laps_graph_launch", "laps_graph_destroy", "laps_buffer", "laps_destroy", "laps_status_string",
@@ -94,6 +94,7 @@ def lib():
         "laps_step_adjusted": (I32, [P, I64]),
         "laps_ensemble_stats": (I32, [P, P, P]),
         "laps_target_eval": (I32, [P, I32, P, P, P, I64, P]),
+        "laps_eval": (I32, [P, P, P, P]),
         "laps_philox_words": (I32, [P, P, I64, U64, P]),
         "laps_philox_normals": (I32, [U64, I64, I64, U64, U32, U32, I32, P, P]),
         "laps_time_gradient": (I32, [P, I32, P]),
@@ -334,6 +335,32 @@ class Sampler:
         _check(lib().laps_kernel_log_read(self.ctx, ctypes.byref(n), ctypes.byref(ms)), self.ctx)
         return n.value, ms.value
 
+    def eval(self, x, grad: bool = True):
+        """log p [N] (float64) and gradient [N, d] of the sampler's target at
+        positions x ([N, d] or padded [N, ld]) through the context
+        (laps_eval): works for every target kind; enqueued on the sampler's
+        stream between steps, the sampler's state is left alone."""
+        torch = _torch()
+        dt = _state_dtype(self.prec)
+        if x.shape[0] != self.N:
+            raise ValueError(f"x needs {self.N} rows")
+        if x.shape[1] != self.ld or x.dtype != dt or not x.is_contiguous():
+            xp = torch.zeros((self.N, self.ld), dtype=dt, device=x.device)
+            xp[:, :self.d] = x[:, :self.d].to(dt)
+        else:
+            xp = x
+        lp = torch.empty(self.N, dtype=torch.float64, device=x.device)
+        g = torch.empty((self.N, self.ld), dtype=dt, device=x.device) if grad else None
+        if self.target.kind == CALLBACK:
+            self.target.buffers.append(xp)
+        try:  # a callback runs inside this call, so x is registered only meanwhile
+            _check(lib().laps_eval(self.ctx, ctypes.c_void_p(xp.data_ptr()), ctypes.c_void_p(lp.data_ptr()),
+                                   ctypes.c_void_p(g.data_ptr()) if grad else None), self.ctx)
+        finally:
+            if self.target.kind == CALLBACK:
+                self.target.buffers.pop()
+        return lp, (g[:, :self.d] if grad else None)
+
     def time_gradient(self, n_reps: int = 20) -> float:
         """Mean milliseconds of one ensemble gradient evaluation (HIP events on the sampler's stream)."""
         ms = ctypes.c_float(0.0)
@@ -435,12 +462,14 @@ def philox_normals(seed: int, n_chains: int, d: int, t: int, tag: int, substep: 
 _LOG_DENSITY_FN = None
 
 
-def log_density(target: "Target", x):
+def log_density(target, x):
     """log p of the rows of x ([n, d]) as a differentiable torch function: the
-    forward pass is one launch of the library's target kernel (laps_target_eval,
-    log p and gradient together), the backward pass scales the saved gradient
-    by the incoming one.  For the targets with a standalone evaluation
-    (diagonal Gaussian, stochastic volatility, phi^4)."""
+    forward pass evaluates log p and its gradient together in the library's
+    target kernels, the backward pass scales the saved gradient by the
+    incoming one.  target is a Target (standalone evaluation, laps_target_eval:
+    diagonal Gaussian, stochastic volatility, phi^4, any n) or a Sampler
+    (laps_eval through its context: every target kind, including logistic
+    regression and the dense Gaussian, with x of the sampler's chain count)."""
     global _LOG_DENSITY_FN
     torch = _torch()
     if _LOG_DENSITY_FN is None:

@@ -231,3 +231,7 @@ def test_dynamics_validation(L):
         assert _ws(L, c, t)[0] == L.OK
     c.dynamics = 2
     assert _ws(L, c, t)[0] == L.EINVAL
+
+
+def test_eval_entry_point_rejects_null(L):
+    assert L.lib().laps_eval(None, None, None, None) == L.EINVAL
