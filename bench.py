@@ -23,7 +23,9 @@ by HIP events on the stream it runs on (logistic regression: the gradient kernel
 against HBM, its rows of x, u (and g) read and written once per chain).
 time_to_bias: wall-clock and gradients per chain until the squared bias of
 the second moments b^2_max first drops below 0.01 on the diagonal Gaussian
-(closed-form moments), FP64 and FP32 state.
+(closed-form moments), FP64 and FP32 state; the same on the rotated
+ill-conditioned Gaussian, and on the logistic-regression posterior (bf16 and
+plain FP64 GPU paths, reference moments from the FP64 oracle).
 cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload.
 f64_gpu: the same run with the plain FP64 path.
 """
@@ -150,25 +152,39 @@ def cpu_baseline(w, n_chains=256, n_unadj=10, n_adj=1):
 
 
 # --------------------------------------------------------------------------- time to bias
-def time_to_bias(prec, threshold=0.01, target="gauss"):
-    """A Gaussian with closed-form moments, 1024 chains, d = 100, the paper's
-    automatic switch: the diagonal Gaussian ("gauss") or the rotated
-    ill-conditioned one ("ill").  Walks the run step by step (untimed)
-    computing b^2_i = (E[x_i^2] - s2_i)^2 / (2 s2_i^2), s2_i the target's
-    variance of x_i, from the ensemble after every unadjusted step and every
-    transition, finds the first crossing of b^2_max < threshold, then times a
-    fresh identical run truncated there (the run is deterministic for its
-    seed)."""
-    import torch
-    from paper_2601_16696_amd import laps, workloads
+def _bias_reference(target):
+    """Workload and the exact E[x_i^2], Var[x_i^2] of its target: closed forms
+    for the two Gaussians (zero mean: E = s2, Var = 2 s2^2), the FP64
+    oracle's reference moments for logistic regression."""
+    from paper_2601_16696_amd import workloads
+    if target == "logreg":
+        ref = json.load(open(os.path.join(ROOT, "tests", "golden", "logreg_n5000_d100_moments.json")))
+        return workloads.logreg(), np.array(ref["E_x2"]), np.array(ref["Var_x2"])
     w = workloads.gaussian() if target == "gauss" else workloads.ill_gaussian()
+    s2 = np.asarray(w["sigma2"] if target == "gauss" else w["cov_diag"])
+    return w, s2, 2.0 * s2 * s2
+
+
+def time_to_bias(prec, threshold=0.01, target="gauss"):
+    """The paper's automatic switch on a target with known second moments:
+    the diagonal Gaussian ("gauss"), the rotated ill-conditioned one ("ill")
+    or the logistic-regression posterior ("logreg", 4096 chains, reference
+    moments from the FP64 oracle).  Walks the run step by step (untimed)
+    computing b^2_i = (E[x_i^2] - E_p[x_i^2])^2 / Var_p[x_i^2] (section "Bias")
+    from the ensemble after every unadjusted step and every transition, finds
+    the first crossing of b^2_max < threshold, then times a fresh identical
+    run truncated there (the run is deterministic for its seed)."""
+    import torch
+    from paper_2601_16696_amd import laps
+    w, e_ref, v_ref = _bias_reference(target)
     cfg = dict(switch_policy=0, max_steps_unadj=N_UNADJ, max_steps_total=N_UNADJ + 15 * N_ADJ)
     s = laps.Sampler(w, prec, **cfg)
-    s2 = torch.as_tensor(w["sigma2"] if target == "gauss" else w["cov_diag"], device="cuda:0", dtype=torch.float64)
+    e_t = torch.as_tensor(e_ref, device="cuda:0", dtype=torch.float64)
+    v_t = torch.as_tensor(v_ref, device="cuda:0", dtype=torch.float64)
 
     def b2():
         x = s.positions().to(torch.float64)
-        b = ((x * x).mean(0) - s2) ** 2 / (2.0 * s2 * s2)
+        b = ((x * x).mean(0) - e_t) ** 2 / v_t
         return float(b.max()), float(b.mean())
 
     n_u = n_a = 0
@@ -437,6 +453,13 @@ def main():
             "criterion": "first step with b2_max < 0.01",
             "paper_laps_grads_context": 308,
             "f64": time_to_bias("f64", target="ill"), "f32": time_to_bias("f32", target="ill")}
+        lb, l64 = time_to_bias("bf16", target="logreg"), time_to_bias("f64", target="logreg")
+        line["time_to_bias_logistic"] = {
+            "workload": "logreg_n5000_d100_N4096, automatic switch; E_p[x_i^2] and Var_p[x_i^2] from the FP64 oracle "
+                        "(8 x 64 chains, 60 pooled MAMS transitions each; tests/golden/logreg_n5000_d100_moments.json)",
+            "criterion": "first step with b2_max < 0.01",
+            "bf16": lb, "f64": l64,
+            "speedup_of_mixed": (l64["ms"] / lb["ms"]) if lb.get("ms") and l64.get("ms") else None}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, **CPU_SAMPLE[args.workload])
     print(json.dumps(line))
