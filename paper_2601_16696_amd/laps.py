@@ -478,12 +478,13 @@ def log_density(target, x):
             def forward(ctx, xx, tgt):
                 lp, g = tgt.eval(xx, grad=True)
                 ctx.save_for_backward(g)
+                ctx.xdtype = xx.dtype
                 return lp.to(xx.dtype)
 
             @staticmethod
             def backward(ctx, gout):
                 (g,) = ctx.saved_tensors
-                return gout[:, None].to(g.dtype) * g, None
+                return (gout[:, None].to(torch.float64) * g.to(torch.float64)).to(ctx.xdtype), None
 
         _LOG_DENSITY_FN = _LogDensity
     return _LOG_DENSITY_FN.apply(x, target)

@@ -120,3 +120,17 @@ def test_log_density_bf16_logistic_through_the_context(gpu, orc):
         dr = 2.0**-9 * np.abs(y - sig) + 0.25 * dz + 1e-7
         bound_g = np.abs(X).T @ dr + 1e-5 * (np.abs(X).T @ np.abs(y - sig)) + 1e-6 * np.abs(th_all[m])
         assert np.all(np.abs(g[m].cpu().numpy().astype(np.float64) - g_ref) <= bound_g)
+
+
+def test_log_density_mixed_sampler_double_input(gpu):
+    """A bf16/FP32-state sampler evaluated at FP64 positions: the gradient
+    comes back in the input's dtype."""
+    import torch
+    w = workloads.logreg(n_chains=16, n=200, d=20)
+    s = gpu.Sampler(w, "bf16")
+    x = s.positions().double().clone().requires_grad_(True)
+    lp = gpu.log_density(s, x)
+    lp.sum().backward()
+    assert lp.dtype == torch.float64 and x.grad.dtype == torch.float64
+    _, g = s.eval(x.detach())
+    assert torch.allclose(x.grad, g.double())
