@@ -141,8 +141,8 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape
   if (s.split) {
     s.G = (int)(N < 64 ? N : 64);
   } else {
-    int64_t gmax = 512;
-    if (const char *e = getenv("LAPS_GRID")) gmax = atol(e) > 0 ? atol(e) : gmax;
+    // at most 512 workgroups (two per CU): each writes one partial row of the statistics
+    const int64_t gmax = 512;
     s.G = (int)(need < gmax ? need : gmax);
   }
   s.shmem = fixed + body(block);
