@@ -306,6 +306,8 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
   }
   Shape s;
   if (!shape_for(cfg, tg, s)) return why = "dimension too large for this build", LAPS_EUNSUPPORTED;
+  // a workgroup of gfx950 holds at most 160 KiB of LDS
+  if (s.shmem_sig > 160 * 1024) return why = "team shape needs more than 160 KiB of LDS", LAPS_EUNSUPPORTED;
   if (tg->kind == LAPS_LOGREG && cfg->prec != LAPS_F64 && cfg->prec != LAPS_MIXED_BF16)
     return why = "logistic regression runs in LAPS_F64 or LAPS_MIXED_BF16", LAPS_EUNSUPPORTED;
   return LAPS_OK;
@@ -619,13 +621,6 @@ extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, 
   c->pS = reinterpret_cast<double *>(w + L.pS);
   c->pW = reinterpret_cast<double *>(w + L.pW);
   c->pPart = reinterpret_cast<double *>(w + L.pPart);
-  if (c->shmem_sig > 160 * 1024) {
-    // a workgroup of gfx950 holds at most 160 KiB of LDS
-    delete c;
-    g_last_global = "team shape needs more than 160 KiB of LDS";
-    return LAPS_EUNSUPPORTED;
-  }
-
   CtlArgs ca = ctl_args(c);
   hipError_t e;
   if ((e = hipMemsetAsync(c->shiftK, 0, (size_t)c->ld * 8, c->stream)) != hipSuccess ||

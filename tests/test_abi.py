@@ -235,3 +235,14 @@ def test_dynamics_validation(L):
 
 def test_eval_entry_point_rejects_null(L):
     assert L.lib().laps_eval(None, None, None, None) == L.EINVAL
+
+
+def test_dimension_limits(L):
+    # FP64: 2 octs per lane on 512-lane teams; FP32: 6 octs, within the MAMS kernel's 160 KiB of LDS
+    for prec, ok_d, bad_d in ((0, 8192, 8200), (1, 20000, 21000)):
+        c, t = _cfg_target(L, kind=0, N=4, d=ok_d)
+        c.prec = prec
+        assert _ws(L, c, t)[0] == L.OK
+        c, t = _cfg_target(L, kind=0, N=4, d=bad_d)
+        c.prec = prec
+        assert _ws(L, c, t)[0] != L.OK

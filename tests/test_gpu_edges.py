@@ -101,3 +101,33 @@ def test_steps_after_the_automatic_switch_are_no_ops(gpu):
     st = s.stats()
     import torch
     assert st["t"] == 4 and st["phase"] == 1 and torch.equal(s.positions(), x)
+
+
+# The largest dimensions the per-chain kernels take: FP64 keeps at most 2 octs
+# per lane on 512-lane teams (d = 8192); FP32 up to 6, bounded by the MAMS
+# kernel's LDS (the per-dim constants and the preconditioner, two rows of d
+# floats, within 160 KiB: d = 20000)
+@pytest.mark.parametrize("prec,d,N", [("f64", 8192, 6), ("f32", 20000, 4)])
+def test_maximum_dimension(gpu, orc, prec, d, N):
+    w = workloads.gaussian(n_chains=N, d=d, seed_data=1020, seed_x0=2020, seed_rng=3020, x0_scale=1.0)
+    cfg = dict(switch_policy=1, max_steps_unadj=5, max_steps_total=5 + 15)
+    o = orc.Ensemble(orc.Target.from_workload(w), N, w["seed"], **cfg)
+    o.init(w["x0"])
+    s = gpu.Sampler(w, prec, **cfg)
+    for _ in range(5):
+        sg = s.stats()
+        o.set_hyper(sg["eps"], sg["L"])
+        o.step_unadjusted(1)
+        s.step_unadjusted(1)
+    tol = 1e-10 if prec == "f64" else 1e-4
+    err = _rel_rows(s.positions().cpu().numpy(), o.array("x"))
+    assert np.max(err) < tol, np.max(err)
+    o.set_hyper(s.stats()["eps"], 0.0)
+    o.step_adjusted(1)
+    s.step_adjusted(1)
+    assert s.stats()["t"] == o.stats()["t"] == 20
+    acc_o, acc_g = o.array("acc"), s.buffer("acc").cpu().numpy()
+    same = np.abs(acc_o - acc_g) < (1e-8 if prec == "f64" else 1e-3)
+    assert same.mean() >= 0.5
+    err = _rel_rows(s.positions().cpu().numpy(), o.array("x"))
+    assert np.all(err[same] < tol), err
