@@ -138,3 +138,41 @@ def test_logistic_full_size_sampled_gradients(gpu, orc):
         dr = 2.0**-9 * np.abs(y - sig) + 0.25 * dz + 1e-7
         bound_g = np.abs(X).T @ dr + 1e-5 * (np.abs(X).T @ np.abs(y - sig)) + 1e-6 * np.abs(th)
         assert np.all(np.abs(g_all[m] - g_ref) <= bound_g), (m, np.max(np.abs(g_all[m] - g_ref) / bound_g))
+
+
+def test_fp32_gaussian_100_steps_replayed(gpu, orc):
+    """FP32 state against the FP64 oracle over 100 unadjusted steps at the
+    full C1 size, with the oracle taking the GPU's (eps, L): 99% of the
+    chains within 1e-4 and every chain within 1e-3.  The few chains beyond
+    1e-4 (2e-4 at most, measured) are the cold start's stiffest ones, where
+    the velocity map amplifies single-precision rounding over 100 steps."""
+    w = workloads.gaussian()
+    o, s = _pair(gpu, orc, w, "f32", switch_policy=1, max_steps_unadj=1000)
+    for _ in range(100):
+        sg = s.stats()
+        o.set_hyper(sg["eps"], sg["L"])
+        o.step_unadjusted(1)
+        s.step_unadjusted(1)
+    err = _rel_rows(s.positions().cpu().numpy(), o.array("x"))
+    q = np.quantile(err, [0.5, 0.9, 0.99, 1.0])
+    assert q[2] < 1e-4 and q[3] < 1e-3, q
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_run_moments_within_monte_carlo_error(gpu, prec):
+    """The benchmark's whole C1 run (1000 unadjusted steps, 67 MAMS
+    transitions) on the GPU: the final ensemble's second moments against the
+    exact ones, b_i^2 M = (E_M[x_i^2] - s2_i)^2 M / (2 s2_i^2) ~ chi^2_1 across
+    the 100 dimensions (Kolmogorov-Smirnov), and the acceptance rate at the
+    target 0.7."""
+    from scipy import stats
+    w = workloads.gaussian()
+    s = gpu.Sampler(w, prec, switch_policy=1, max_steps_unadj=1000, max_steps_total=1000 + 15 * 67)
+    s.step_unadjusted(1000)
+    s.step_adjusted(67)
+    st = s.stats()
+    assert st["t"] == 2005 and st["phase"] == 2 and st["grads_per_chain"] == 1 + 1000 + 67 * 30
+    x = s.positions().cpu().numpy().astype(np.float64)
+    b2M = ((x**2).mean(0) - w["sigma2"]) ** 2 / (2 * w["sigma2"] ** 2) * w["n_chains"]
+    assert stats.kstest(b2M, stats.chi2(1).cdf).pvalue > 1e-3
+    assert abs(st["acc_mean"] - 0.7) < 0.05
