@@ -297,7 +297,7 @@ __device__ __forceinline__ void lds_dma16(const bf16x8 *src, bf16x8 *lds_dst) {
 
 template <int KC, bool FULL>
 __device__ __forceinline__ void lr_block_lean(const bf16x8 *L, const float *Y, int lane, int q, int nvalid,
-                                              const bf16x8 (&thi)[KC], const bf16x8 (&tlo)[KC],
+                                              int dtiles, const bf16x8 (&thi)[KC], const bf16x8 (&tlo)[KC],
                                               f32x4 (&gacc)[2 * KC], double &lacc) {
   f32x4 z[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
@@ -335,10 +335,13 @@ __device__ __forceinline__ void lr_block_lean(const bf16x8 *L, const float *Y, i
       prod *= ope;
     }
   lacc += 0.6931471805599453 * ((double)la - 0.5 * (double)lb) - (double)__logf(prod);
+  // output tiles of 16 dims past d (all padding, e.g. the eighth for d = 100) are skipped
 #pragma unroll
   for (int dc = 0; dc < 2 * KC; ++dc) {
-    const bf16x8 bfr = L[2 * KC * 64 + dc * 64 + lane];
-    gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr, rb, gacc[dc], 0, 0, 0);
+    if (dc < dtiles) {
+      const bf16x8 bfr = L[2 * KC * 64 + dc * 64 + lane];
+      gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr, rb, gacc[dc], 0, 0, 0);
+    }
   }
 }
 
@@ -375,8 +378,9 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
   // loop-invariant per-thread offset.
   constexpr int kBlk = 2 * KC * 64;
   const bf16x8 *baseF = XF + (int64_t)b0 * kBlk, *baseB = XB + (int64_t)b0 * kBlk;
+  const int dtiles = (int)((a.d + 15) / 16);  // output tiles holding dims < d
   int offk[kPer], halfk[kPer];
-  bool fwdk[kPer];
+  bool fwdk[kPer], usek[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int c = tid + 512 * k;
@@ -384,12 +388,14 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
     halfk[k] = half;
     fwdk[k] = f < kBlk;
     offk[k] = half * kBlk + (f < kBlk ? f : f - kBlk);
+    // backward fragments of an all-padding output tile are never read
+    usek[k] = f < kBlk || (f - kBlk) / 64 < dtiles;
   }
   auto stage = [&](int it, int buf) {
     const int64_t step = (int64_t)it * 2 * kBlk;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      if (b0 + 2 * it + halfk[k] < b1)
+      if (usek[k] && b0 + 2 * it + halfk[k] < b1)
         lds_dma16((fwdk[k] ? baseF : baseB) + step + offk[k], lds + buf * kBuf + 512 * k + 64 * wave);
     }
     if (tid < 16) {
@@ -432,9 +438,9 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
       const float *Y = reinterpret_cast<const float *>(lds + (it & 1) * kBuf + 2 * kFrag + 8 * rh);
       const int64_t nv = n - 32 * blk;
       if (nv >= 32)
-        lr_block_lean<KC, true>(L, Y, lane, q, 32, thi, tlo, gacc, lacc);
+        lr_block_lean<KC, true>(L, Y, lane, q, 32, dtiles, thi, tlo, gacc, lacc);
       else
-        lr_block_lean<KC, false>(L, Y, lane, q, (int)nv, thi, tlo, gacc, lacc);
+        lr_block_lean<KC, false>(L, Y, lane, q, (int)nv, dtiles, thi, tlo, gacc, lacc);
     }
     // this thread's fragments of iteration it + 1 are in LDS; the barrier
     // publishes everyone's and retires the reads of the current buffer
