@@ -14,6 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liblaps_hip.so")
+CAPI = os.path.join(PKG, "laps_capi_run")
 OBJ = os.path.join(PKG, "_build")
 SOURCES = ["laps_api.hip", "laps_local.hip", "laps_local_gauss.hip", "laps_local_sv.hip", "laps_local_phi4.hip",
            "laps_control.hip", "laps_logreg.hip", "laps_dense.hip", "laps_rng.hip"]
@@ -39,6 +40,12 @@ def build(verbose: bool = True) -> str:
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", OUT + ".tmp"]
     subprocess.run(cmd, check=True)
     os.replace(OUT + ".tmp", OUT)
+    # a plain C consumer of the ABI (HIP runtime C API only), used by the tests
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
+           "-I/opt/rocm/include", os.path.join(CSRC, "laps_capi_run.c"), "-o", CAPI + ".tmp",
+           "-L" + PKG, "-llaps_hip", "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,$ORIGIN"]
+    subprocess.run(cmd, check=True)
+    os.replace(CAPI + ".tmp", CAPI)
     if verbose:
         print("built", OUT)
     return OUT
