@@ -107,3 +107,22 @@ def test_callback_error_fails_the_step(gpu):
     s.step_unadjusted(2)                                                                     # calls 2, 3
     with pytest.raises(gpu.LapsError, match="gradient callback returned 1"):
         s.step_unadjusted(1)
+
+
+def test_callback_eval_through_the_context(gpu):
+    """laps_eval on a callback target calls the callback at the caller's
+    positions (not the sampler's state) and returns its log p and gradient."""
+    import torch
+    w = workloads.gaussian(n_chains=32, d=24, x0_scale=1.0)
+    wc, calls = _gauss_callback(w, torch.float64)
+    s = gpu.Sampler(wc, "f64")
+    n0 = calls[0]
+    before = s.positions().clone()
+    x = torch.as_tensor(np.asarray(w["x0"]) * 0.5 - 0.2, device="cuda:0")
+    lp, g = s.eval(x)
+    torch.cuda.synchronize()
+    assert calls[0] == n0 + 1
+    inv = torch.as_tensor(1.0 / np.asarray(w["sigma2"]), device="cuda:0")
+    assert torch.allclose(g, -x * inv, rtol=1e-15, atol=0)
+    assert torch.allclose(lp, -0.5 * (x * x * inv).sum(1), rtol=1e-14, atol=0)
+    assert torch.equal(s.positions(), before)
