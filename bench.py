@@ -155,17 +155,20 @@ def cpu_baseline(w, n_chains=256, n_unadj=10, n_adj=1):
 def _bias_reference(target):
     """Workload and the exact E[x_i^2], Var[x_i^2] of its target: closed forms
     for the two Gaussians (zero mean: E = s2, Var = 2 s2^2), the FP64
-    oracle's reference moments for logistic regression."""
+    oracle's reference moments for logistic regression and stochastic
+    volatility."""
     from paper_2601_16696_amd import workloads
-    if target == "logreg":
-        ref = json.load(open(os.path.join(ROOT, "tests", "golden", "logreg_n5000_d100_moments.json")))
-        return workloads.logreg(), np.array(ref["E_x2"]), np.array(ref["Var_x2"])
+    if target in ("logreg", "stochvol"):
+        name = "logreg_n5000_d100_moments.json" if target == "logreg" else "stochvol_T2427_moments.json"
+        ref = json.load(open(os.path.join(ROOT, "tests", "golden", name)))
+        w = workloads.logreg() if target == "logreg" else workloads.stochvol()
+        return w, np.array(ref["E_x2"]), np.array(ref["Var_x2"])
     w = workloads.gaussian() if target == "gauss" else workloads.ill_gaussian()
     s2 = np.asarray(w["sigma2"] if target == "gauss" else w["cov_diag"])
     return w, s2, 2.0 * s2 * s2
 
 
-def time_to_bias(prec, threshold=0.01, target="gauss"):
+def time_to_bias(prec, threshold=0.01, target="gauss", n_adj=N_ADJ):
     """The paper's automatic switch on a target with known second moments:
     the diagonal Gaussian ("gauss"), the rotated ill-conditioned one ("ill")
     or the logistic-regression posterior ("logreg", 4096 chains, reference
@@ -177,7 +180,7 @@ def time_to_bias(prec, threshold=0.01, target="gauss"):
     import torch
     from paper_2601_16696_amd import laps
     w, e_ref, v_ref = _bias_reference(target)
-    cfg = dict(switch_policy=0, max_steps_unadj=N_UNADJ, max_steps_total=N_UNADJ + 15 * N_ADJ)
+    cfg = dict(switch_policy=0, max_steps_unadj=N_UNADJ, max_steps_total=N_UNADJ + 15 * n_adj)
     s = laps.Sampler(w, prec, **cfg)
     e_t = torch.as_tensor(e_ref, device="cuda:0", dtype=torch.float64)
     v_t = torch.as_tensor(v_ref, device="cuda:0", dtype=torch.float64)

@@ -40,3 +40,17 @@ def test_reference_moments_against_laplace():
     # reference noise: b^2 contribution (se / std)^2 well below 0.01
     assert np.all(v > 0) and np.max(se / np.sqrt(v)) < 0.03
     assert all(0.55 < a < 0.85 for a in r["acceptance"])
+
+
+def test_stochvol_reference_is_stationary_and_precise():
+    """The stochastic-volatility reference (tests/golden/stochvol_moments.py,
+    FP64 oracle): the first and second halves of the pooled transitions agree
+    within their Monte Carlo error across all 2429 dimensions (no drift left
+    after burn-in), and the reference's own noise stays well below the bias
+    threshold it is used against."""
+    r = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "stochvol_T2427_moments.json")))
+    e, v, se = np.array(r["E_x2"]), np.array(r["Var_x2"]), np.array(r["se_E_x2"])
+    assert e.shape == v.shape == se.shape == (2429,)
+    assert np.all(e > 0) and np.all(v > 0)
+    assert r["halves_z_max"] < 4.5 and 0.4 < r["halves_z_median"] < 0.9
+    assert r["max_se_over_std"] < 0.05

@@ -176,3 +176,38 @@ def test_full_run_moments_within_monte_carlo_error(gpu, prec):
     b2M = ((x**2).mean(0) - w["sigma2"]) ** 2 / (2 * w["sigma2"] ** 2) * w["n_chains"]
     assert stats.kstest(b2M, stats.chi2(1).cdf).pvalue > 1e-3
     assert abs(st["acc_mean"] - 0.7) < 0.05
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_stochvol_full_dimension_mams(gpu, orc, prec):
+    """The stochastic-volatility MAMS kernel instance the benchmark runs at
+    T = 2427 (FP32: 64-lane teams with 5 octs per lane; FP64: 2 octs per lane
+    on 192-lane teams) and the MN4 integrator, on 64 chains: 5 replayed
+    unadjusted steps, then 2 transitions against the oracle from the same
+    state and step size; chains with the same Metropolis decision agree to
+    the precision's bound."""
+    w = workloads.stochvol(n_chains=64)
+    lanes = 64 if prec == "f32" else 192
+    cfg = dict(switch_policy=1, max_steps_unadj=5, max_steps_total=5 + 15 * 2, team_lanes=lanes)
+    o = orc.Ensemble(orc.Target.from_workload(w), 64, w["seed"],
+                     **{k: v for k, v in cfg.items() if k != "team_lanes"})
+    o.init(w["x0"])
+    s = gpu.Sampler(w, prec, **cfg)
+    for _ in range(5):
+        sg = s.stats()
+        o.set_hyper(sg["eps"], sg["L"])
+        o.step_unadjusted(1)
+        s.step_unadjusted(1)
+    tol = 1e-4 if prec == "f32" else 1e-10
+    for _ in range(2):
+        o.set_hyper(s.stats()["eps"], 0.0)
+        o.step_adjusted(1)
+        s.step_adjusted(1)
+        so, sg = o.stats(), s.stats()
+        assert so["integrator"] == sg["integrator"] == 2 and so["t"] == sg["t"]
+    acc_o, acc_g = o.array("acc"), s.buffer("acc").cpu().numpy()
+    err = _rel_rows(s.positions().cpu().numpy(), o.array("x"))
+    same = err < 1e-2
+    assert same.mean() >= (0.9 if prec == "f32" else 1.0), same.mean()
+    assert np.max(err[same]) < tol, np.max(err[same])
+    assert np.max(np.abs(acc_g - acc_o)[same]) < (2e-3 if prec == "f32" else 1e-8)
