@@ -77,16 +77,18 @@ def test_unadjusted_bias_bound_on_gaussian(orc):
     assert D > 10 * 2.0 / M  # the bias is resolved, not just noise
 
 
-@pytest.mark.parametrize("which_d,eps", [(4, 3.2), (30, 11.0)])
-def test_mams_preserves_exact_gaussian(orc, which_d, eps):
+@pytest.mark.parametrize("which_d,eps,integ", [(4, 3.2, 0), (30, 11.0, 0), (30, 16.0, 2)])
+def test_mams_preserves_exact_gaussian(orc, which_d, eps, integ):
     """Start from exact draws; transitions at a large step (low acceptance)
-    leave E[x_i^2] at sigma_i^2 within Monte Carlo error."""
+    leave E[x_i^2] at sigma_i^2 within Monte Carlo error.  integ 0 takes the
+    default (MN2 at these d); integ 2 forces the fourth-order MN4, whose
+    negative kick coefficient the energy accounting must also cover."""
     rng = np.random.default_rng(which_d)
     d = which_d
     M = 60000 if d == 4 else 12000
     s2 = np.linspace(0.3, 3.0, d)
     x = rng.normal(size=(M, d)) * np.sqrt(s2)
-    e = _gauss_ens(orc, s2, M, seed=7, acc_tol=2.0, max_steps_total=10**6)
+    e = _gauss_ens(orc, s2, M, seed=7, acc_tol=2.0, max_steps_total=10**6, integrator_adj=integ)
     e.init(x)
     e.do_switch()
     e.set_array("sigma", np.sqrt(s2) * np.linspace(0.7, 1.4, d))  # any fixed preconditioner is valid
