@@ -232,99 +232,6 @@ def time_to_bias(prec, threshold=0.01, target="gauss", n_adj=N_ADJ):
     return out
 
 
-# --------------------------------------------------------------------------- batched
-def _mix_prec(w, mixed=True):
-    if not mixed:
-        return "f64"
-    return "bf16" if w["kind"] == "logreg" else "f32"
-
-
-def batched(steps, warmup, seg_unadj=100, seg_adj=10):
-    """16 samplers, each on its own stream, replayed from segment graphs."""
-    import torch
-    from paper_2601_16696_amd import laps, workloads
-    ws = workloads.batched_mix()
-    streams = [torch.cuda.Stream() for _ in ws]
-    samplers = []
-    for w, st in zip(ws, streams):
-        with torch.cuda.stream(st):
-            samplers.append(laps.Sampler(w, _mix_prec(w), **_cfg()))
-    torch.cuda.synchronize()
-    x0s = [s.x.clone() for s in samplers]
-    assert N_UNADJ % seg_unadj == 0
-    n_full, tail = divmod(N_ADJ - seg_adj, seg_adj)
-    g_first = laps.RunGraph(samplers, seg_unadj, 0, restart=True, x0s=x0s)
-    g_unadj = laps.RunGraph(samplers, seg_unadj, 0)
-    g_adj_first = laps.RunGraph(samplers, 0, seg_adj)
-    g_adj = laps.RunGraph(samplers, 0, seg_adj)
-    g_adj_tail = laps.RunGraph(samplers, 0, tail) if tail else None
-
-    def run():
-        g_first.launch()
-        for _ in range(N_UNADJ // seg_unadj - 1):
-            g_unadj.launch()
-        g_adj_first.launch()
-        for _ in range(n_full):
-            g_adj.launch()
-        if g_adj_tail is not None:
-            g_adj_tail.launch()
-
-    for _ in range(warmup):
-        run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        run()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) / steps * 1e3
-    sts = [s.stats() for s in samplers]
-    grads = sum(st["grads_per_chain"] * w["n_chains"] for st, w in zip(sts, ws))
-    # the same mixed-precision runs one after another, eager
-    t0 = time.perf_counter()
-    for s, x0, st in zip(samplers, x0s, streams):
-        with torch.cuda.stream(st):
-            s.restart(x0[:, :s.d])
-            s.step_unadjusted(N_UNADJ)
-            s.step_adjusted(N_ADJ)
-        torch.cuda.synchronize()
-    ms_seq = (time.perf_counter() - t0) * 1e3
-    # dominant kernel: the logistic target with the most gradient flops
-    lr = [(4.0 * w["X"].shape[0] * w["d"] * w["n_chains"], k) for k, w in enumerate(ws) if w["kind"] == "logreg"]
-    flops, kmax = max(lr)
-    with torch.cuda.stream(streams[kmax]):
-        grad_ms = samplers[kmax].time_gradient(20)
-    info = dict(ms=ms, value=grads / (ms * 1e-3), grads=grads, ms_sequential_mixed=ms_seq,
-                targets=[dict(name=w["name"], chains=w["n_chains"], d=w["d"], precision=_mix_prec(w),
-                              grads_per_chain=st["grads_per_chain"], acc_mean=st["acc_mean"],
-                              n_nonfinite=st["n_nonfinite"]) for w, st in zip(ws, sts)],
-                dominant=dict(target=ws[kmax]["name"], flops=flops, grad_ms=grad_ms))
-    del g_first, g_unadj, g_adj_first, g_adj, g_adj_tail
-    return info, ws
-
-
-def batched_f64_sample(ws, n_unadj=20, n_adj=1):
-    """Plain FP64 path, the 16 targets one after another on one stream, on a
-    bounded sample (n_unadj steps + n_adj transitions each): chain-gradients/s."""
-    import torch
-    from paper_2601_16696_amd import laps
-    total_grads, total_s = 0, 0.0
-    for w in ws:
-        s = laps.Sampler(w, "f64", **_cfg(n_unadj, n_adj))
-        s.step_unadjusted(2)
-        s.restart()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.step_unadjusted(n_unadj)
-        s.step_adjusted(n_adj)
-        torch.cuda.synchronize()
-        total_s += time.perf_counter() - t0
-        total_grads += s.stats()["grads_per_chain"] * w["n_chains"]
-        del s
-        torch.cuda.empty_cache()
-    return dict(value=total_grads / total_s, seconds=total_s,
-                sample=f"{n_unadj} unadjusted steps + {n_adj} transition per target, targets one after another")
-
-
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,33 +254,11 @@ def main():
 
     if args.workload == "batched":
         # The concurrent replay of the 16-target mix from segment graphs faulted the GPU (an illegal
-        # memory access) on its first run and no cause has been shown yet; it stays disabled until one is.
+        # memory access) on its first run and no cause has been shown; its logistic targets with d > 128
+        # are refused by the library since, so the mix is not run.
         print("bench.py --workload batched is disabled: its graph replay of the 16-target mix faulted the GPU "
-              "and the cause is not yet found", file=sys.stderr)
+              "and the cause is not found", file=sys.stderr)
         sys.exit(3)
-        info, ws = batched(args.steps, args.warmup)
-        dom = info["dominant"]
-        achieved = dom["flops"] / (dom["grad_ms"] * 1e-3) / 1e12
-        line = {
-            "metric": METRIC, "value": info["value"], "unit": "chain-grad evals/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": info["ms"], "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32", "data": "synthetic",
-            "config": {"workload": "batched mix: 8 diagonal Gaussians (d 10..2000, FP32) + 8 logistic regressions "
-                                   "((n, d) (1000, 20)..(20000, 300), bf16), full LAPS runs replayed "
-                                   "concurrently from segment graphs", "chains": sum(w["n_chains"] for w in ws),
-                       "targets": 16, "parallelism": "single GPU, one stream per target"},
-            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                         "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
-                         "kernel": f"bf16 gradient of {dom['target']}", "kernel_ms": dom["grad_ms"]},
-            "sequential_mixed_ms": info["ms_sequential_mixed"],
-            "speedup_of_concurrent_over_sequential": info["ms_sequential_mixed"] / info["ms"],
-            "targets": info["targets"],
-        }
-        if not args.no_f64:
-            f64 = batched_f64_sample(ws)
-            line["f64_gpu"] = dict(f64, speedup_of_mixed_batched=info["value"] / f64["value"])
-        print(json.dumps(line))
-        return
 
     prec = args.prec or default_prec
     w = getattr(workloads, gen)()
@@ -408,13 +293,16 @@ def main():
     else:
         rs = 8 if prec == "f64" else 4
         unadj_ms, adj_ms = step_kernel_times(w, prec)
-        rows = 4 if args.workload == "gauss" else 6  # x, u read and written (+ the kept gradient g)
-        work = float(rows * rs * d * N)
+        # algorithmic bytes of one unadjusted step: x and u read and written once per chain (4 rows);
+        # the stochastic-volatility and phi^4 kernels also keep g in HBM (2 more rows), an implementation
+        # choice reported apart and not counted
+        work = float(4 * rs * d * N)
+        kept_g = float(2 * rs * d * N) if args.workload != "gauss" else 0.0
         achieved = work / (kern["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_unadj (unadjusted step)",
                 "kernel_ms": kern["ms"], "launches_timed": kern["launches"], "isolated_kernel_ms": unadj_ms,
-                "algorithmic_bytes_per_launch": work,
+                "algorithmic_bytes_per_launch": work, "kept_gradient_bytes_per_launch": kept_g,
                 "adjusted_transition_kernel_ms": adj_ms, "gradient_only_ms": r["grad_ms"]}
         precision = "fp64 throughout" if prec == "f64" else "fp32 state, fp64 energy error and reductions"
         extra = {}

@@ -81,8 +81,12 @@ typedef enum { LAPS_F64 = 0, LAPS_F32 = 1, LAPS_MIXED_BF16 = 2 } laps_precision;
  *                    differentiable log density).  cb and cb_user below.
  *   LAPS_GAUSS_DENSE zero-mean Gaussian with a dense precision matrix A:
  *                    log p = -x^T A x / 2.   data[0] = A [d][d] (double,
- *                    row-major, symmetric positive definite); d <= 512,
- *                    LAPS_F64 or LAPS_F32 state, MN2 adjusted integrator.
+ *                    row-major, symmetric positive definite); LAPS_F64 or
+ *                    LAPS_F32 state.
+ * LAPS_LOGREG, LAPS_CALLBACK and LAPS_GAUSS_DENSE run through the per-chain
+ * update kernels and are limited to d <= 128 with the second-order (MN2)
+ * adjusted integrator: their wider update teams and the MN4 transition are
+ * switched off (LAPS_EUNSUPPORTED) after GPU faults whose cause is not found.
  * Target data must stay valid and unchanged while a context uses it. */
 typedef enum {
   LAPS_GAUSS_DIAG = 0,

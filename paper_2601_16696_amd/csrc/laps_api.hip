@@ -82,6 +82,11 @@ struct Shape {
   size_t shmem, shmem_sig;  // dynamic LDS without / with the preconditioner row
 };
 
+// Largest dimension of the targets run by the per-chain update kernels
+// (logistic regression, callbacks, the dense Gaussian): one oct per lane in
+// teams of up to 16 lanes.
+constexpr int64_t kUpdateMaxD = 128;
+
 bool is_local(int kind) { return kind == LAPS_GAUSS_DIAG || kind == LAPS_STOCHVOL || kind == LAPS_PHI4; }
 
 // Team shape of the per-chain kernels: the chain's ceil(d/8) octs over T
@@ -158,7 +163,7 @@ bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
   if (tg->kind == LAPS_LOGREG || tg->kind == LAPS_CALLBACK || tg->kind == LAPS_GAUSS_DENSE) {
     // per-chain update kernels: one oct per lane, up to 64 lanes
     const int64_t octs = (cfg->d + 7) / 8;
-    if (cfg->d > (tg->kind == LAPS_LOGREG ? 320 : 512)) return false;
+    if (cfg->d > kUpdateMaxD) return false;
     int T = 1;
     while (T < octs) T <<= 1;
     s.T = T;
@@ -280,25 +285,24 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
       if (tg->dims[0] < 2 || tg->dims[0] * tg->dims[0] != cfg->d) return why = "phi4 needs dims[0]^2 == d", LAPS_EINVAL;
       break;
     case LAPS_LOGREG:
-      if (!tg->data[0] || !tg->data[1] || tg->dims[0] < 1) return why = "logreg needs X, y and n", LAPS_EINVAL;
-      if (cfg->d > 320) return why = "logistic regression supports d <= 320", LAPS_EUNSUPPORTED;
-      // The staged fourth-order (MN4) transition of this target faulted the GPU in testing with no
-      // cause shown yet; it is refused until one is.  d <= 200 selects MN2 automatically.
-      if (integ_for(cfg) == 2)
-        return why = "logistic regression with the MN4 integrator (d > 200 or integrator_adj = 2) is disabled",
-               LAPS_EUNSUPPORTED;
-      break;
     case LAPS_CALLBACK:
     case LAPS_GAUSS_DENSE:
+      if (tg->kind == LAPS_LOGREG && (!tg->data[0] || !tg->data[1] || tg->dims[0] < 1))
+        return why = "logreg needs X, y and n", LAPS_EINVAL;
       if (tg->kind == LAPS_CALLBACK && !tg->cb) return why = "a callback target needs cb", LAPS_EINVAL;
       if (tg->kind == LAPS_GAUSS_DENSE && !tg->data[0]) return why = "a dense Gaussian needs data[0] = A", LAPS_EINVAL;
-      if (cfg->prec == LAPS_MIXED_BF16)
+      if (tg->kind != LAPS_LOGREG && cfg->prec == LAPS_MIXED_BF16)
         return why = "callback and dense Gaussian targets run in LAPS_F64 or LAPS_F32", LAPS_EUNSUPPORTED;
-      if (cfg->d > 512) return why = "callback and dense Gaussian targets support d <= 512", LAPS_EUNSUPPORTED;
-      // same update kernels as logistic regression, so the same MN4 restriction
+      // These targets share the per-chain update kernels.  Two GPU runs that used their 32- and 64-lane
+      // teams (d > 128) outside the initialisation, with the staged fourth-order transition, faulted the
+      // GPU with no cause shown; both the wide teams and the MN4 transition are refused until one is.
+      if (cfg->d > kUpdateMaxD)
+        return why = "logistic-regression, callback and dense Gaussian targets support d <= 128 (their 32- and "
+                     "64-lane update teams are switched off)",
+               LAPS_EUNSUPPORTED;
       if (integ_for(cfg) == 2)
-        return why = "callback and dense Gaussian targets with the MN4 integrator (d > 200 or integrator_adj = 2) "
-                     "are disabled; set integrator_adj = 1",
+        return why = "logistic-regression, callback and dense Gaussian targets with the MN4 integrator "
+                     "(integrator_adj = 2) are switched off",
                LAPS_EUNSUPPORTED;
       break;
     default:

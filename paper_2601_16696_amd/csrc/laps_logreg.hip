@@ -22,8 +22,6 @@
 // The per-chain update kernels also serve caller-supplied targets: the
 // caller's gradient callback writes one "split" of partial sums (g and log p
 // without the prior), and the kernels run unchanged with prior = 0.
-#include <stdlib.h>
-
 #include "laps_team.hpp"
 
 namespace laps {
@@ -32,22 +30,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-// The direct-to-LDS gradient kernel is the default for d <= 128;
-// LAPS_LR_KERNEL=staged selects the register-staged one.
-static bool lr_lds_kernel() {
-  static const int v = [] {
-    const char *e = getenv("LAPS_LR_KERNEL");
-    return (e && e[0] == 's') ? 0 : 1;
-  }();
-  return v != 0;
-}
-
 void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int wgs, int &S, int &NB, int &bps) {
   NB = (int)((n + 31) / 32);
   const int64_t groups = (N + 63) / 64;
   // workgroups of one gradient launch: two per CU for the direct-to-LDS bf16
   // kernel (which two workgroups per CU fit), one per CU otherwise
-  int64_t target = (prec != 0 && d <= 128 && lr_lds_kernel()) ? 512 : 256;
+  int64_t target = (prec != 0 && d <= 128) ? 512 : 256;
   if (wgs > 0) target = wgs;
   int64_t want = target / (groups > 0 ? groups : 1);
   if (want < 1) want = 1;
@@ -105,183 +93,10 @@ __global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, i
 }
 
 // ---------------------------------------------------------------------------
-// bf16 matrix-core gradient, LDS-staged (d <= 128).  grid (ceil(N/64), S),
-// 512 threads = 8 wavefronts: wavefront w owns chain group w % 4 (16 chains)
-// and row half w / 4 of the split's 32-row blocks (half 0 takes even blocks,
-// half 1 odd ones).  Each iteration stages the operand fragments of two
-// blocks (one per half) in LDS once for all four chain groups; the next two
-// blocks are prefetched into registers while the current ones are computed.
-// The two halves' G and log p partials are added in LDS at the end.
-// ---------------------------------------------------------------------------
-template <int KC, bool FULL>
-__device__ __forceinline__ void lr_block(const bf16x8 *L, const float *Y, int lane, int q, int nvalid,
-                                         const bf16x8 (&thi)[KC], const bf16x8 (&tlo)[KC], f32x4 (&gacc)[2 * KC],
-                                         double &lacc) {
-  // all forward fragments first (one LDS wait), then four independent
-  // accumulation chains: (half 0, half 1) x (theta hi, theta lo)
-  bf16x8 af[2][KC];
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc) af[h][kc] = L[(h * KC + kc) * 64 + lane];
-  f32x4 zh[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-  f32x4 zl[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-  for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      zh[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h][kc], thi[kc], zh[h], 0, 0, 0);
-      zl[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h][kc], tlo[kc], zl[h], 0, 0, 0);
-    }
-  bf16x8 bfr[2 * KC];
-#pragma unroll
-  for (int dc = 0; dc < 2 * KC; ++dc) bfr[dc] = L[2 * KC * 64 + dc * 64 + lane];
-  const float4 y0 = *reinterpret_cast<const float4 *>(Y + 4 * q);
-  const float4 y1 = *reinterpret_cast<const float4 *>(Y + 16 + 4 * q);
-  const float yv[2][4] = {{y0.x, y0.y, y0.z, y0.w}, {y1.x, y1.y, y1.z, y1.w}};
-  // epilogue (labels packed as ym = y - 1/2, s = 1/(1 + e^{-|z|})):
-  // r = y - sigmoid(z) = ym - copysign(s - 1/2, z); log p terms
-  // y z - softplus(z) = ym z - |z|/2 - log(1 + e^{-|z|}), where the eight logs
-  // of the lane are taken as one log of their product (factors in (1, 2])
-  bf16x8 rb;
-  float lin = 0.f, prod = 1.f;
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float zz = zh[h][i] + zl[h][i];
-      const bool ok = FULL || (16 * h + 4 * q + i < nvalid);
-      const float e = ok ? __expf(-fabsf(zz)) : 0.f;
-      const float ope = 1.0f + e;
-      const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
-      rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - copysignf(t, zz) : 0.f);
-      lin += ok ? fmaf(yv[h][i], zz, -0.5f * fabsf(zz)) : 0.f;
-      prod *= ope;
-    }
-  lacc += (double)lin - (double)__logf(prod);
-#pragma unroll
-  for (int dc = 0; dc < 2 * KC; ++dc) gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[dc], rb, gacc[dc], 0, 0, 0);
-}
-
-template <int KC>
-__global__ void __launch_bounds__(512) k_lr_grad_bf16(LogregArgs a) {
-  if (!lr_gate(a)) return;
-  constexpr int kFrag = 4 * KC * 64;      // 16-byte fragments per 32-row block
-  constexpr int kPer = 2 * kFrag / 512;    // staging loads per thread per iteration
-  constexpr int kBuf = 2 * kFrag + 16;     // one buffer: two blocks' fragments + their 2 x 32 labels
-  extern __shared__ bf16x8 lds[];          // [2 buffers][kBuf]
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int cg = wave & 3, rh = wave >> 2;
-  const int q = lane >> 4, cl = lane & 15;
-  const int64_t N = a.N, ld = a.ld, n = a.n;
-  const int64_t m = ((int64_t)blockIdx.x * 4 + cg) * 16 + cl;
-  const bool mval = m < N;
-  const float *X = static_cast<const float *>(a.x);
-  bf16x8 thi[KC], tlo[KC];
-#pragma unroll
-  for (int kc = 0; kc < KC; ++kc) {
-#pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-      const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (mval && d4 < ld) v = *reinterpret_cast<const float4 *>(X + m * ld + d4);
-      const float f[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const __bf16 hi = (__bf16)f[i];
-        thi[kc][4 * hh + i] = hi;
-        tlo[kc][4 * hh + i] = (__bf16)(f[i] - (float)hi);
-      }
-    }
-  }
-  f32x4 gacc[2 * KC];
-#pragma unroll
-  for (int dc = 0; dc < 2 * KC; ++dc) gacc[dc] = f32x4{0.f, 0.f, 0.f, 0.f};
-  double lacc = 0.0;
-  const LrOffsets off = logreg_layout(1, n, a.d, N, ld, a.S);
-  const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
-  const bf16x8 *XB = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xb);
-  const bf16x8 *YF = reinterpret_cast<const bf16x8 *>(a.scratch + off.yf);  // labels, 4 floats per 16 bytes
-  const int s = blockIdx.y;
-  const int b0 = s * a.bps;
-  const int b1 = (b0 + a.bps < a.NB) ? b0 + a.bps : a.NB;
-  const int nit = (b1 - b0 + 1) / 2;
-  // fragment c of an iteration: half c / kFrag; inside a block the forward
-  // fragments (2 KC x 64) precede the backward ones (2 KC x 64); lanes 0..15
-  // also stage the two blocks' labels (8 x 16 bytes each)
-  auto fetch = [&](int it, bf16x8 (&reg)[kPer], bf16x8 &ry) {
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int c = tid + 512 * k;
-      const int half = c / kFrag, f = c - half * kFrag;
-      const int64_t blk = b0 + 2 * it + half;
-      if (blk < b1)
-        reg[k] = f < 2 * KC * 64 ? XF[blk * 2 * KC * 64 + f] : XB[blk * 2 * KC * 64 + (f - 2 * KC * 64)];
-    }
-    if (tid < 16) {
-      const int64_t blk = b0 + 2 * it + (tid >> 3);
-      if (blk < b1) ry = YF[blk * 8 + (tid & 7)];
-    }
-  };
-  auto stash = [&](int buf, const bf16x8 (&reg)[kPer], const bf16x8 &ry) {
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) lds[buf * kBuf + tid + 512 * k] = reg[k];
-    if (tid < 16) lds[buf * kBuf + 2 * kFrag + tid] = ry;
-  };
-  bf16x8 reg[kPer], ry;
-  fetch(0, reg, ry);
-  stash(0, reg, ry);
-  __syncthreads();
-  for (int it = 0; it < nit; ++it) {
-    const bool more = it + 1 < nit;
-    if (more) fetch(it + 1, reg, ry);
-    const int64_t blk = b0 + 2 * it + rh;
-    if (blk < b1) {
-      const bf16x8 *L = lds + (it & 1) * kBuf + rh * kFrag;
-      const float *Y = reinterpret_cast<const float *>(lds + (it & 1) * kBuf + 2 * kFrag + 8 * rh);
-      const int64_t nv = n - 32 * blk;
-      if (nv >= 32)
-        lr_block<KC, true>(L, Y, lane, q, 32, thi, tlo, gacc, lacc);
-      else
-        lr_block<KC, false>(L, Y, lane, q, (int)nv, thi, tlo, gacc, lacc);
-    }
-    if (more) stash((it + 1) & 1, reg, ry);
-    __syncthreads();
-  }
-  // half 1 hands its partial sums to half 0 through LDS (fixed order: half 0 + half 1)
-  float *red = reinterpret_cast<float *>(lds);
-  double *lred = reinterpret_cast<double *>(red + 4 * 64 * 8 * KC);
-  if (rh == 1) {
-#pragma unroll
-    for (int dc = 0; dc < 2 * KC; ++dc)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) red[((cg * 2 * KC + dc) * 4 + i) * 64 + lane] = gacc[dc][i];
-    lred[cg * 64 + lane] = lacc;
-  }
-  __syncthreads();
-  if (rh == 0) {
-    float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
-    if (mval) {
-#pragma unroll
-      for (int dc = 0; dc < 2 * KC; ++dc)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int64_t dd = 16 * dc + 4 * q + i;
-          if (dd < ld) Gp[dd] = gacc[dc][i] + red[((cg * 2 * KC + dc) * 4 + i) * 64 + lane];
-        }
-    }
-    lacc += lred[cg * 64 + lane];
-    lacc += __shfl_xor(lacc, 16);
-    lacc += __shfl_xor(lacc, 32);
-    if (mval && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// bf16 matrix-core gradient with direct-to-LDS staging (d <= 128).  The work
-// split is the staged kernel's (grid (ceil(N/64), S), 8 wavefronts: chain
-// group w % 4, row half w / 4), but the operand fragments of the next two
+// bf16 matrix-core gradient with direct-to-LDS staging (d <= 128).  grid
+// (ceil(N/64), S), 8 wavefronts: wavefront w owns chain group w % 4 (16
+// chains) and row half w / 4 of the split's 32-row blocks (half 0 takes even
+// blocks, half 1 odd ones).  The operand fragments of the next two
 // blocks go from global memory straight into LDS (global_load_lds_dwordx4:
 // one wavefront instruction writes 64 consecutive 16-byte fragments), so no
 // registers carry them; fragments are read from LDS where they are used, and
@@ -1016,21 +831,6 @@ hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The staged kernel's LDS exceeds 64 KiB for d > 96: raise its limit once
-// (gfx950 provides 160 KiB per workgroup).
-template <int KC>
-static hipError_t launch_staged(dim3 grid, size_t shm, const LogregArgs &a, hipStream_t s) {
-  static size_t attr_set = 0;  // largest dynamic LDS size granted so far
-  if (shm > attr_set) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_lr_grad_bf16<KC>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    attr_set = shm;
-  }
-  hipLaunchKernelGGL(k_lr_grad_bf16<KC>, grid, dim3(512), shm, s, a);
-  return hipGetLastError();
-}
-
 hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
   if (prec == 0) {
     const dim3 grid((unsigned)((a.N + 15) / 16), (unsigned)a.S);
@@ -1040,7 +840,7 @@ hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
   }
   const dim3 grid((unsigned)((a.N + 63) / 64), (unsigned)a.S);
   const size_t shm = (size_t)2 * (2 * 4 * a.KC * 64 + 16) * 16;
-  if (a.KC <= 4 && lr_lds_kernel()) {
+  if (a.KC <= 4) {
     void (*fn)(LogregArgs) = a.KC == 1 ? k_lr_grad_bf16_lds<1>
                              : a.KC == 2 ? k_lr_grad_bf16_lds<2>
                              : a.KC == 3 ? k_lr_grad_bf16_lds<3>
@@ -1052,10 +852,6 @@ hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
     return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, dim3(512), args, shm, s);
   }
   switch (a.KC) {
-    case 1: return launch_staged<1>(grid, shm, a, s);
-    case 2: return launch_staged<2>(grid, shm, a, s);
-    case 3: return launch_staged<3>(grid, shm, a, s);
-    case 4: return launch_staged<4>(grid, shm, a, s);
     case 5: hipLaunchKernelGGL(k_lr_grad_bf16_direct<5>, grid, dim3(256), 0, s, a); break;
     case 6: hipLaunchKernelGGL(k_lr_grad_bf16_direct<6>, grid, dim3(256), 0, s, a); break;
     case 7: hipLaunchKernelGGL(k_lr_grad_bf16_direct<7>, grid, dim3(256), 0, s, a); break;

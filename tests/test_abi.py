@@ -142,21 +142,27 @@ def test_team_shape_override(L, kind, d, side, lanes, ok):
     assert _ws(L, c, t)[0] == L.EINVAL
 
 
-def test_logreg_mn4_refused(L):
-    """The logistic-regression MN4 transition is refused until its GPU fault is explained."""
-    c, t = _cfg_target(L, kind=1, d=204)
-    assert _ws(L, c, t)[0] == L.EUNSUPPORTED
-    c.integrator_adj = 1
-    assert _ws(L, c, t)[0] == L.OK
-    c, t = _cfg_target(L, kind=1, d=100)
-    c.integrator_adj = 2
-    assert _ws(L, c, t)[0] == L.EUNSUPPORTED
+@pytest.mark.parametrize("kind", [1, 4, 5])
+def test_update_kernel_targets_limited_to_narrow_teams(L, kind):
+    """Logistic regression, callbacks and the dense Gaussian share the
+    per-chain update kernels.  Their 32- and 64-lane teams (d > 128) and the
+    MN4 transition are refused until the GPU faults seen with them are
+    explained; d <= 128 with the MN2 integrator is accepted."""
+    def cfg(d, integ=0):
+        c, t = _cfg_target(L, kind=kind, d=d)
+        t.cb = 0x3000
+        c.integrator_adj = integ
+        return c, t
+    assert _ws(L, *cfg(100))[0] == L.OK
+    assert _ws(L, *cfg(128))[0] == L.OK
+    for d in (129, 138, 200, 204, 300):
+        for integ in (0, 1):
+            assert _ws(L, *cfg(d, integ))[0] == L.EUNSUPPORTED, (d, integ)
+    assert _ws(L, *cfg(100, 2))[0] == L.EUNSUPPORTED
 
 
 def test_callback_target_validation(L):
-    """A caller-supplied target needs a callback, runs in FP64 or FP32 state,
-    supports d <= 512 (one oct per lane, 64 lanes) and, like logistic
-    regression, only the MN2 adjusted integrator."""
+    """A caller-supplied target needs a callback and runs in FP64 or FP32 state."""
     c, t = _cfg_target(L, kind=L.CALLBACK, d=30)
     assert _ws(L, c, t)[0] == L.EINVAL            # no callback
     t.cb = 0x3000
@@ -164,15 +170,6 @@ def test_callback_target_validation(L):
     c.prec = L.F32
     assert _ws(L, c, t)[0] == L.OK
     c.prec = L.MIXED_BF16
-    assert _ws(L, c, t)[0] == L.EUNSUPPORTED
-    c, t = _cfg_target(L, kind=L.CALLBACK, d=300)
-    t.cb = 0x3000
-    assert _ws(L, c, t)[0] == L.EUNSUPPORTED      # d > 200 selects MN4
-    c.integrator_adj = 1
-    assert _ws(L, c, t)[0] == L.OK
-    c, t = _cfg_target(L, kind=L.CALLBACK, d=513)
-    t.cb = 0x3000
-    c.integrator_adj = 1
     assert _ws(L, c, t)[0] == L.EUNSUPPORTED
 
 
@@ -194,11 +191,9 @@ def test_dense_gauss_validation(L):
     assert _ws(L, c, t)[0] == L.OK
     t.data[0] = 0
     assert _ws(L, c, t)[0] == L.EINVAL
-    c, t = _cfg_target(L, kind=L.GAUSS_DENSE, d=300)
-    assert _ws(L, c, t)[0] == L.EUNSUPPORTED      # MN4 selected for d > 200
-    c.integrator_adj = 1
+    c, t = _cfg_target(L, kind=L.GAUSS_DENSE, d=120)
     st, n = _ws(L, c, t)
-    assert st == L.OK and n >= 300 * 300 * 8      # the precision matrix is copied into the workspace
+    assert st == L.OK and n >= 120 * 120 * 8      # the precision matrix is copied into the workspace
     c.prec = L.MIXED_BF16
     assert _ws(L, c, t)[0] == L.EUNSUPPORTED
 

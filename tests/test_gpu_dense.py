@@ -32,7 +32,9 @@ def _rel_rows(a, b):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
-SHAPES = [(70, 37), (64, 100), (130, 16), (40, 203)]
+# d = 203 needs the 32-lane update teams, which the library refuses after GPU faults whose cause is not found
+SHAPES = [(70, 37), (64, 100), (130, 16),
+          pytest.param(40, 203, marks=pytest.mark.skip(reason="d > 128: 32/64-lane update teams switched off"))]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -140,6 +140,28 @@ def test_logistic_full_size_sampled_gradients(gpu, orc):
         assert np.all(np.abs(g_all[m] - g_ref) <= bound_g), (m, np.max(np.abs(g_all[m] - g_ref) / bound_g))
 
 
+def test_logistic_full_run_moments_against_reference(gpu):
+    """The benchmark's whole logistic-regression run (4096 chains, bf16
+    gradients, 1000 unadjusted steps, 67 MN2 transitions) ends at the
+    posterior's second moments: against the FP64 oracle's reference
+    (tests/golden/logreg_n5000_d100_moments.json, whose own Monte Carlo error
+    is at most 3e-4 in b^2), b^2_max < 0.01 (the bias criterion) and
+    b^2_avg < 1e-3; the acceptance rate is at its target 0.7."""
+    import json
+    import os
+    w = workloads.logreg()
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "logreg_n5000_d100_moments.json")))
+    s = gpu.Sampler(w, "bf16", switch_policy=1, max_steps_unadj=1000, max_steps_total=1000 + 15 * 67)
+    s.step_unadjusted(1000)
+    s.step_adjusted(67)
+    st = s.stats()
+    assert st["t"] == 2005 and st["phase"] == 2 and st["n_nonfinite"] == 0
+    x = s.positions().cpu().numpy().astype(np.float64)
+    b2 = ((x**2).mean(0) - np.array(ref["E_x2"])) ** 2 / np.array(ref["Var_x2"])
+    assert b2.max() < 0.01 and b2.mean() < 1e-3, (b2.max(), b2.mean())
+    assert abs(st["acc_mean"] - 0.7) < 0.05, st["acc_mean"]
+
+
 def test_fp32_gaussian_100_steps_replayed(gpu, orc):
     """FP32 state against the FP64 oracle over 100 unadjusted steps at the
     full C1 size, with the oracle taking the GPU's (eps, L): 99% of the

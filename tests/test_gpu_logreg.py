@@ -43,7 +43,14 @@ def _rel_rows(a, b):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
-@pytest.mark.parametrize("shape", [(100, 300, 37), (64, 32, 100), (130, 5000, 100), (40, 77, 300)])
+# d > 128 runs the per-chain update kernels with 32- or 64-lane teams, which the library refuses (and
+# the refusal is tested on the CPU in test_abi.py) after two GPU faults whose cause is not found
+WIDE = pytest.mark.skip(reason="d > 128 needs the 32/64-lane update teams, switched off after GPU faults "
+                               "whose cause is not found; the library refuses these shapes")
+
+
+@pytest.mark.parametrize("shape", [(100, 300, 37), (64, 32, 100), (130, 5000, 100),
+                                   pytest.param((40, 77, 300), marks=WIDE)])
 def test_gradient_at_init_f64(gpu, orc, shape):
     N, n, d = shape
     w = _w(N, n, d)
@@ -62,14 +69,14 @@ def test_gradient_at_init_f64(gpu, orc, shape):
 # (n, d) of the batched mix's logistic targets reach every k-chunk count of the
 # staged (d <= 128) and direct-load gradient kernels; fewer chains, with n
 # shortened where the oracle would be slow
-C5_LR = [(48, 1000, 20), (40, 1534, 29), (36, 2354, 43), (24, 3611, 64), (20, 2000, 94), (16, 1200, 138),
-         (12, 800, 204), (8, 600, 300)]
-# d > 200 would select MN4, which is refused for this target (see test_fourth_order_transitions); the
-# gradient kernels at those d are checked with the MN2 integrator requested explicitly
+C5_LR = [(48, 1000, 20), (40, 1534, 29), (36, 2354, 43), (24, 3611, 64), (20, 2000, 94),
+         pytest.param((16, 1200, 138), marks=WIDE), pytest.param((12, 800, 204), marks=WIDE),
+         pytest.param((8, 600, 300), marks=WIDE)]
 MN2 = dict(integrator_adj=1)
 
 
-@pytest.mark.parametrize("shape", [(100, 300, 37), (64, 32, 100), (130, 5000, 100), (40, 77, 300)] + C5_LR)
+@pytest.mark.parametrize("shape", [(100, 300, 37), (64, 32, 100), (130, 5000, 100),
+                                   pytest.param((40, 77, 300), marks=WIDE)] + C5_LR)
 def test_gradient_at_init_bf16_error_bounds(gpu, orc, shape):
     N, n, d = shape
     w = _w(N, n, d)
@@ -152,8 +159,80 @@ def test_mixed_adjusted_runs_and_accepts(gpu, orc):
     assert np.all(np.isfinite(s.positions().cpu().numpy()))
 
 
-@pytest.mark.skip(reason="the logistic-regression MN4 transition faulted the GPU (illegal memory access) with no "
-                         "cause shown yet; the library refuses that configuration until one is")
+@pytest.mark.parametrize("shape", [(100, 300, 37), (96, 1000, 100)])
+def test_mixed_transitions_against_oracle_on_identical_states(gpu, orc, shape):
+    """The bf16 adjusted phase (MN2 MAMS transitions, the bulk of the
+    logistic-regression run's gradients) against the FP64 oracle.  Before
+    every transition the oracle takes the GPU's positions (its FP32 state,
+    exactly), its step size and, at the switch, its preconditioner; the
+    oracle's own FP64 log p and gradient at those positions start its
+    trajectory.  Per transition: the step counter is identical; the energy
+    errors agree to the bf16 bound (|dDelta| < 5e-2: z carries 2^-17 relative
+    error from the hi/lo split, r is rounded to bf16); chains with the same
+    Metropolis decision agree to 5e-3 relative (their trajectories are
+    steered by bf16 gradients for 15 steps); at most 10% of the chains (and no
+    more than the energy differences explain) flip a decision."""
+    import torch
+    N, n, d = shape
+    w = _w(N, n, d, seed=21)
+    n_adj = 4
+    cfg = dict(switch_policy=1, max_steps_unadj=10, max_steps_total=10 + 15 * n_adj)
+    o = _oracle(orc, w, **cfg)
+    s = gpu.Sampler(w, "bf16", **cfg)
+    ot = orc.Target.from_workload(w)
+    for _ in range(10):
+        sg = s.stats()
+        o.set_hyper(sg["eps"], sg["L"])
+        o.step_unadjusted(1)
+        s.step_unadjusted(1)
+    o.do_switch()
+    worst_dD, worst_x, flips_total = 0.0, 0.0, 0
+    for k in range(n_adj):
+        sg = s.stats()
+        assert sg["t"] == o.stats()["t"] == 10 + 15 * k
+        xk = s.positions().cpu().numpy().astype(np.float64)
+        s.step_adjusted(1)
+        torch.cuda.synchronize()
+        sig = s.buffer("sigma").cpu().numpy().astype(np.float64)
+        lg = [ot.logp_grad(r) for r in xk]
+        o.set_array("x", xk)
+        o.set_array("g", np.array([r[1] for r in lg]))
+        o.set_array("logp", np.array([r[0] for r in lg]))
+        o.set_array("sigma", sig)
+        o.set_hyper(sg["eps"], sg["L"])
+        o.mams_move()
+        o.adj_control()
+        sg2, so = s.stats(), o.stats()
+        assert sg2["t"] == so["t"] == 10 + 15 * (k + 1) and sg2["n_nonfinite"] == 0
+        dg, do = s.buffer("delta").cpu().numpy(), o.array("delta")
+        dD = np.abs(dg - do)
+        worst_dD = max(worst_dD, float(dD.max()))
+        assert np.max(dD) < 5e-2, (k, np.max(dD))
+        xg, xo = s.positions().cpu().numpy().astype(np.float64), o.array("x")
+        acc_g = np.any(xg != xk, axis=1)
+        acc_o = np.any(xo != xk, axis=1)
+        flip = acc_g != acc_o
+        flips_total += int(flip.sum())
+        # a flip needs the uniform between e^{-Delta_gpu} and e^{-Delta_oracle}
+        U = np.array([orc.mh_uniform(w["seed"], m, 10 + 15 * k) for m in range(N)])
+        lo = np.minimum(np.exp(-dg), np.exp(-do))
+        hi = np.maximum(np.exp(-dg), np.exp(-do))
+        assert np.all((U[flip] >= lo[flip]) & (U[flip] < hi[flip]))
+        same = ~flip
+        # rejected on both sides: restored to the identical start
+        assert np.array_equal(xg[same & ~acc_g], xk[same & ~acc_g])
+        both = same & acc_g
+        if np.any(both):
+            err = _rel_rows(xg[both], xo[both])
+            worst_x = max(worst_x, float(err.max()))
+            assert np.max(err) < 5e-3, (k, np.max(err))
+    assert flips_total <= max(2, 0.1 * N * n_adj), flips_total
+    print(f"bf16 MAMS vs FP64 oracle (N={N}, n={n}, d={d}): max |dDelta| {worst_dD:.2e}, "
+          f"max rel x err {worst_x:.2e}, decision flips {flips_total}/{N * n_adj}")
+
+
+@pytest.mark.skip(reason="the logistic-regression MN4 transition (d = 204, 32-lane update teams) faulted the GPU "
+                         "(illegal memory access) with no cause shown yet; the library refuses that configuration")
 @pytest.mark.parametrize("prec", ["f64", "bf16"])
 def test_fourth_order_transitions(gpu, orc, prec):
     """d > 200 selects the MN4 integrator for the adjusted phase: five
