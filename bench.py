@@ -49,7 +49,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the bf16 gradient kernel on the logistic-regression workload, from FETCH_SIZE
 # and WRITE_SIZE counters scaled by what they read for a plain copy of known size; kept with the counter
 # summary under profiles/ and reset to None whenever the kernel changes.
-LR_GRAD_TRAFFIC_BYTES = 34.99e6  # k_lr_grad_bf16_lds<4>: 21.09 MB fetched + 13.91 MB written
+LR_GRAD_TRAFFIC_BYTES = None
 N_UNADJ, N_ADJ = 1000, 67
 # the dominant kernel's launches bracketed by HIP events inside the timed runs: one in LOG_EVERY
 LOG_EVERY = int(os.environ.get("LAPS_BENCH_LOG_EVERY", "10"))
@@ -274,7 +274,7 @@ def main():
         roof = {"bound": "mfma" if prec == "bf16" else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": LR_GRAD_TRAFFIC_BYTES if prec == "bf16" else None,
                 "traffic_unit": "bytes per launch",
-                "kernel": "k_lr_grad_bf16_lds<4>" if prec == "bf16" else "k_lr_grad_f64", "kernel_ms": kern["ms"],
+                "kernel": "k_lr_grad_bf16_pair<4, 7>" if prec == "bf16" else "k_lr_grad_f64", "kernel_ms": kern["ms"],
                 "launches_timed": kern["launches"], "isolated_kernel_ms": r["grad_ms"],
                 "algorithmic_flops_per_launch": work}
         precision = ("bf16 matrix-core gradient, fp32 state, fp64 energy error and reductions"

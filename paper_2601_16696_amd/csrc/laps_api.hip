@@ -377,6 +377,7 @@ LogregArgs logreg_args(laps_ctx *c, int gate) {
   } else {
     logreg_splits(a.n, a.N, c->cfg.prec, a.d, c->cfg.grad_workgroups, a.S, a.NB, a.bps);
     a.prior = 1;
+    a.wy_term = c->cfg.prec == LAPS_F64 ? 0 : 1;
   }
   a.KC = (int)((a.d + 31) / 32);
   a.T = c->T;

@@ -129,6 +129,7 @@ struct LogregArgs {
   double cb0, ca0, cbk, cak;
   int cK;
   int prior;               // 1: add the N(0, I) prior of logistic regression to the partial sums; 0: caller's log p
+  int wy_term;             // 1: add theta . (X^T (y - 1/2)), left out of the bf16 gradient's split sums
   double *logp_out;        // LR_EVAL: log p output [N]
   void *g_out;             // LR_EVAL: gradient output [N][ld] (or null)
 };
@@ -136,7 +137,7 @@ struct LogregArgs {
 enum { LR_INIT = 0, LR_PRE = 1, LR_POST = 2, LR_MBEGIN = 3, LR_MSTEP = 4, LR_EVAL = 5 };
 
 struct LrOffsets {
-  size_t Xf, Xb, yf, Gp, lp, x0, g0, sc, total;
+  size_t Xf, Xb, yf, wy, Gp, lp, x0, g0, sc, total;
 };
 __host__ __device__ inline size_t lr_al256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -152,6 +153,8 @@ __host__ __device__ inline LrOffsets logreg_layout(int prec, int64_t n, int64_t 
   off = lr_al256(off + (bf ? (size_t)NB * 2 * KC * 64 * 8 * 2 : 0));
   o.yf = off;
   off = lr_al256(off + (bf ? (size_t)NB * 32 * 4 : 0));
+  o.wy = off;
+  off = lr_al256(off + (bf ? (size_t)ld * 8 : 0));
   o.Gp = off;
   off = lr_al256(off + (size_t)S * N * ld * rs);
   o.lp = off;

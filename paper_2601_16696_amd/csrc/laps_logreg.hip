@@ -31,11 +31,13 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int wgs, int &S, int &NB, int &bps) {
+  (void)d;
   NB = (int)((n + 31) / 32);
-  const int64_t groups = (N + 63) / 64;
-  // workgroups of one gradient launch: two per CU for the direct-to-LDS bf16
-  // kernel (which two workgroups per CU fit), one per CU otherwise
-  int64_t target = (prec != 0 && d <= 128) ? 512 : 256;
+  // chain tiles of one gradient launch: 128 chains per bf16 workgroup; the
+  // FP64 kernel is split as if its tiles held 64 chains
+  const int64_t groups = prec != 0 ? (N + 127) / 128 : (N + 63) / 64;
+  // workgroups of one launch: one per CU
+  int64_t target = 256;
   if (wgs > 0) target = wgs;
   int64_t want = target / (groups > 0 ? groups : 1);
   if (want < 1) want = 1;
@@ -57,8 +59,8 @@ __device__ __forceinline__ bool lr_gate(const LogregArgs &a) {
 //   Xb[b][dc][lane][j]    = X[32b + 16(j/4) + 4(lane/16) + j%4][16dc + lane%16]
 //   yf[row]               = y[row] - 1/2 (0 beyond n)
 // ---------------------------------------------------------------------------
-__global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, int64_t d, int KC, int NB,
-                          unsigned short *Xf, unsigned short *Xb, float *yf) {
+__global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, int64_t d, int64_t ld, int KC,
+                          int NB, unsigned short *Xf, unsigned short *Xb, float *yf, double *wy) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nf = (int64_t)NB * 2 * KC * 64;
   if (tid < nf) {
@@ -89,20 +91,44 @@ __global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, i
     return;
   }
   const int64_t t3 = t2 - nbk;
-  if (t3 < (int64_t)NB * 32) yf[t3] = t3 < n ? (float)(y[t3] - 0.5) : 0.0f;
+  if (t3 < (int64_t)NB * 32) {
+    yf[t3] = t3 < n ? (float)(y[t3] - 0.5) : 0.0f;
+    return;
+  }
+  // wy[i] = sum_n X_ni (y_n - 1/2) in FP64, rows in order (zero for i >= d)
+  const int64_t i = t3 - (int64_t)NB * 32;
+  if (i < ld) {
+    double acc = 0.0;
+    if (i < d)
+      for (int64_t r = 0; r < n; ++r)
+        acc += (double)__uint_as_float((unsigned)X[r * d + i] << 16) * (y[r] - 0.5);
+    wy[i] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// bf16 matrix-core gradient with direct-to-LDS staging (d <= 128).  grid
-// (ceil(N/64), S), 8 wavefronts: wavefront w owns chain group w % 4 (16
-// chains) and row half w / 4 of the split's 32-row blocks (half 0 takes even
-// blocks, half 1 odd ones).  The operand fragments of the next two
-// blocks go from global memory straight into LDS (global_load_lds_dwordx4:
-// one wavefront instruction writes 64 consecutive 16-byte fragments), so no
-// registers carry them; fragments are read from LDS where they are used, and
-// theta's hi and lo products accumulate into one register tile.  The kernel
-// keeps to 128 VGPRs, so two workgroups (16 wavefronts) share a CU and one
-// workgroup's matrix-core phase overlaps the other's vector epilogue.
+// bf16 matrix-core gradient (d <= 128).  grid (ceil(N/128), S), 512 threads =
+// 8 wavefronts: wavefront w owns the 32 chains of pair group w % 4 (two
+// 16-chain MFMA tiles, g = 0, 1) and row half w / 4 of the split's 32-row
+// blocks (half 0 takes even blocks, half 1 odd ones).  Each X fragment read
+// from LDS feeds both chain tiles, so LDS traffic per chain is half that of a
+// 16-chain wavefront.  The operand fragments of the next two blocks go from
+// global memory straight into LDS (global_load_lds_dwordx4: one wavefront
+// instruction writes 64 consecutive 16-byte fragments) while the current
+// ones are used; theta's hi and lo products accumulate into one register
+// tile.  One workgroup per CU (two wavefronts per SIMD, up to 256 VGPRs).
+//
+// The products carry z' = z log2(e) (theta is scaled before its hi/lo
+// split), so e^{-|z|} is one base-2 exponential.  With the packed label
+// ym = y - 1/2 and s = 1/(1 + e^{-|z|}):
+//   r = y - sigmoid(z) = ym - copysign(s - 1/2, z')   (s - 1/2 is exact),
+//   y z - softplus(z) = ym z - |z|/2 - log(1 + e^{-|z|}).
+// The kernel sums only the last two terms per chain (|z'| added, the factors
+// 1 + e^{-|z|} in (1, 2] multiplied, one log2 per block); sum_n ym_n z_n =
+// theta . (X^T ym) is linear in theta and is added in FP64 by the update
+// kernels from the precomputed X^T ym.  Rows past n have X = 0 and ym = 0, so
+// they give r = 0 and |z| = 0 and a factor of exactly 2 each, whose log2 (1
+// per row) is subtracted.
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -110,70 +136,75 @@ __device__ __forceinline__ void lds_dma16(const bf16x8 *src, bf16x8 *lds_dst) {
   __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_dst, 16, 0, 0);
 }
 
-template <int KC, bool FULL>
-__device__ __forceinline__ void lr_block_lean(const bf16x8 *L, const float *Y, int lane, int q, int nvalid,
-                                              int dtiles, const bf16x8 (&thi)[KC], const bf16x8 (&tlo)[KC],
-                                              f32x4 (&gacc)[2 * KC], double &lacc) {
-  f32x4 z[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+template <int KC, int DT>
+__device__ __forceinline__ void lr_block_pair(const bf16x8 *L, const float *Y, int lane, int q,
+                                              const bf16x8 (&thi)[2][KC], const bf16x8 (&tlo)[2][KC],
+                                              f32x4 (&gacc)[2][2 * KC], float (&lq)[2]) {
+  f32x4 z[2][2];
 #pragma unroll
-  for (int kc = 0; kc < KC; ++kc)
+  for (int g = 0; g < 2; ++g)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const bf16x8 af = L[(h * KC + kc) * 64 + lane];
-      z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, thi[kc], z[h], 0, 0, 0);
-      z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, tlo[kc], z[h], 0, 0, 0);
-    }
+    for (int h = 0; h < 2; ++h) z[g][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    bf16x8 af[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) af[h] = L[(h * KC + kc) * 64 + lane];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        z[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h], thi[g][kc], z[g][h], 0, 0, 0);
+        z[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h], tlo[g][kc], z[g][h], 0, 0, 0);
+      }
+  }
   const float4 y0 = *reinterpret_cast<const float4 *>(Y + 4 * q);
   const float4 y1 = *reinterpret_cast<const float4 *>(Y + 16 + 4 * q);
   const float yv[2][4] = {{y0.x, y0.y, y0.z, y0.w}, {y1.x, y1.y, y1.z, y1.w}};
-  // The products carry z' = z log2(e) (theta is scaled before its hi/lo
-  // split), so e^{-|z|} is one base-2 exponential.  With the packed label
-  // ym = y - 1/2 and s = 1/(1 + e^{-|z|}):
-  //   r = y - sigmoid(z) = ym - copysign(s - 1/2, z')   (s - 1/2 is exact),
-  //   y z - softplus(z) = ln2 (ym z' - |z'|/2) - log(1 + e^{-|z|}),
-  // with ym z' and |z'| summed apart and the lane's eight logs taken as one
-  // log of their product (factors in (1, 2])
-  bf16x8 rb;
-  float la = 0.f, lb = 0.f, prod = 1.f;
+  bf16x8 rb[2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int g = 0; g < 2; ++g) {
+    float ab = 0.f, prod = 1.f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float zz = z[h][i];
-      const bool ok = FULL || (16 * h + 4 * q + i < nvalid);
-      const float e = ok ? __builtin_amdgcn_exp2f(-fabsf(zz)) : 0.f;
-      const float ope = 1.0f + e;
-      const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
-      rb[4 * h + i] = (__bf16)(ok ? yv[h][i] - copysignf(t, zz) : 0.f);
-      la += ok ? yv[h][i] * zz : 0.f;
-      lb += ok ? fabsf(zz) : 0.f;
-      prod *= ope;
-    }
-  lacc += 0.6931471805599453 * ((double)la - 0.5 * (double)lb) - (double)__logf(prod);
-  // output tiles of 16 dims past d (all padding, e.g. the eighth for d = 100) are skipped
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-  for (int dc = 0; dc < 2 * KC; ++dc) {
-    if (dc < dtiles) {
-      const bf16x8 bfr = L[2 * KC * 64 + dc * 64 + lane];
-      gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr, rb, gacc[dc], 0, 0, 0);
-    }
+      for (int i = 0; i < 4; ++i) {
+        const float zz = z[g][h][i];
+        const float e = __builtin_amdgcn_exp2f(-fabsf(zz));
+        const float ope = 1.0f + e;
+        const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
+        rb[g][4 * h + i] = (__bf16)(yv[h][i] - copysignf(t, zz));
+        ab += fabsf(zz);
+        prod *= ope;
+      }
+    // prod lies in [1, 256]: the hardware log2 is accurate there
+    lq[g] += fmaf(0.5f, ab, __builtin_amdgcn_logf(prod));
   }
+  // the DT output tiles of 16 dims that hold dims < d (a tile wholly past d,
+  // e.g. the eighth for d = 100, is all padding and skipped)
+  bf16x8 bfr[DT];
+#pragma unroll
+  for (int dc = 0; dc < DT; ++dc) bfr[dc] = L[2 * KC * 64 + dc * 64 + lane];
+#pragma unroll
+  for (int dc = 0; dc < DT; ++dc)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) gacc[g][dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[dc], rb[g], gacc[g][dc], 0, 0, 0);
 }
 
-template <int KC>
-__global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
+template <int KC, int DT>
+__global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pair(LogregArgs a) {
   if (!lr_gate(a)) return;
   constexpr int kFrag = 4 * KC * 64;      // 16-byte fragments per 32-row block
   constexpr int kPer = 2 * kFrag / 512;    // fragments per thread per iteration
   constexpr int kBuf = 2 * kFrag + 16;     // one buffer: two blocks' fragments + their 2 x 32 labels
+  constexpr int kBlk = 2 * KC * 64;        // forward (or backward) fragments of one block
   extern __shared__ bf16x8 lds[];          // [2 buffers][kBuf]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int cg = wave & 3, rh = wave >> 2;
+  const int pg = wave & 3, rh = wave >> 2;
   const int q = lane >> 4, cl = lane & 15;
   const int64_t N = a.N, ld = a.ld, n = a.n;
-  const int64_t m = ((int64_t)blockIdx.x * 4 + cg) * 16 + cl;
-  const bool mval = m < N;
+  const int64_t mbase = (int64_t)blockIdx.x * 128 + pg * 32 + cl;  // chain of tile g: mbase + 16 g
   const float *X = static_cast<const float *>(a.x);
   const LrOffsets off = logreg_layout(1, n, a.d, N, ld, a.S);
   const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
@@ -185,15 +216,12 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
   const int nit = (b1 - b0 + 1) / 2;
   // Iteration it stages blocks b0 + 2 it (half 0) and b0 + 2 it + 1 (half 1).
   // Fragment c of a buffer belongs to half c / kFrag; inside a block the
-  // forward fragments (2 KC x 64) precede the backward ones.  A wavefront's 64
-  // fragments of one instruction lie in one block, so the block test is
-  // uniform per wavefront; lanes 0..15 of wavefront 0 also stage the labels.
-  // Both packed forms have 2 KC x 64 fragments per block, so a fragment's
-  // source is a uniform base (advanced by two blocks per iteration) plus a
-  // loop-invariant per-thread offset.
-  constexpr int kBlk = 2 * KC * 64;
+  // forward fragments precede the backward ones.  A wavefront's 64 fragments
+  // of one instruction lie in one block, so the block test is uniform per
+  // wavefront; lanes 0..15 of wavefront 0 also stage the labels.  A
+  // fragment's source is a uniform base (advanced by two blocks per
+  // iteration) plus a loop-invariant per-thread offset.
   const bf16x8 *baseF = XF + (int64_t)b0 * kBlk, *baseB = XB + (int64_t)b0 * kBlk;
-  const int dtiles = (int)((a.d + 15) / 16);  // output tiles holding dims < d
   int offk[kPer], halfk[kPer];
   bool fwdk[kPer], usek[kPer];
 #pragma unroll
@@ -204,7 +232,7 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
     fwdk[k] = f < kBlk;
     offk[k] = half * kBlk + (f < kBlk ? f : f - kBlk);
     // backward fragments of an all-padding output tile are never read
-    usek[k] = f < kBlk || (f - kBlk) / 64 < dtiles;
+    usek[k] = f < kBlk || (f - kBlk) / 64 < DT;
   }
   auto stage = [&](int it, int buf) {
     const int64_t step = (int64_t)it * 2 * kBlk;
@@ -219,29 +247,36 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
     }
   };
   stage(0, 0);
-  bf16x8 thi[KC], tlo[KC];
+  // theta log2(e) of both chain tiles, split into bf16 hi + lo (B operand:
+  // k slot 8q + j of chunk kc is coordinate 32 kc + 16 (j / 4) + 4 q + j % 4)
+  bf16x8 thi[2][KC], tlo[2][KC];
 #pragma unroll
-  for (int kc = 0; kc < KC; ++kc) {
+  for (int g = 0; g < 2; ++g) {
+    const int64_t m = mbase + 16 * g;
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-      const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (mval && d4 < ld) v = *reinterpret_cast<const float4 *>(X + m * ld + d4);
-      // theta log2(e), split into bf16 hi + lo
-      const float f[4] = {v.x * 1.4426950408889634f, v.y * 1.4426950408889634f, v.z * 1.4426950408889634f,
-                          v.w * 1.4426950408889634f};
+    for (int kc = 0; kc < KC; ++kc) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const __bf16 hi = (__bf16)f[i];
-        thi[kc][4 * hh + i] = hi;
-        tlo[kc][4 * hh + i] = (__bf16)(f[i] - (float)hi);
+      for (int hh = 0; hh < 2; ++hh) {
+        const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (m < N && d4 < ld) v = *reinterpret_cast<const float4 *>(X + m * ld + d4);
+        const float f[4] = {v.x * 1.4426950408889634f, v.y * 1.4426950408889634f, v.z * 1.4426950408889634f,
+                            v.w * 1.4426950408889634f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const __bf16 hi = (__bf16)f[i];
+          thi[g][kc][4 * hh + i] = hi;
+          tlo[g][kc][4 * hh + i] = (__bf16)(f[i] - (float)hi);
+        }
       }
     }
   }
-  f32x4 gacc[2 * KC];
+  f32x4 gacc[2][2 * KC];
 #pragma unroll
-  for (int dc = 0; dc < 2 * KC; ++dc) gacc[dc] = f32x4{0.f, 0.f, 0.f, 0.f};
-  double lacc = 0.0;
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int dc = 0; dc < 2 * KC; ++dc) gacc[g][dc] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double lacc[2] = {0.0, 0.0};
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int it = 0; it < nit; ++it) {
@@ -251,11 +286,21 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
     if (blk < b1) {
       const bf16x8 *L = lds + (it & 1) * kBuf + rh * kFrag;
       const float *Y = reinterpret_cast<const float *>(lds + (it & 1) * kBuf + 2 * kFrag + 8 * rh);
+      float lq[2] = {0.f, 0.f};
+      lr_block_pair<KC, DT>(L, Y, lane, q, thi, tlo, gacc, lq);
+      // rows of this lane past n: each contributed a factor 2 (log2 = 1)
       const int64_t nv = n - 32 * blk;
-      if (nv >= 32)
-        lr_block_lean<KC, true>(L, Y, lane, q, 32, dtiles, thi, tlo, gacc, lacc);
-      else
-        lr_block_lean<KC, false>(L, Y, lane, q, (int)nv, dtiles, thi, tlo, gacc, lacc);
+      if (nv < 32) {
+        int pad = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) pad += (16 * h + 4 * q + i >= nv) ? 1 : 0;
+        lq[0] -= (float)pad;
+        lq[1] -= (float)pad;
+      }
+      lacc[0] += (double)lq[0];
+      lacc[1] += (double)lq[1];
     }
     // this thread's fragments of iteration it + 1 are in LDS; the barrier
     // publishes everyone's and retires the reads of the current buffer
@@ -265,125 +310,38 @@ __global__ void __launch_bounds__(512, 4) k_lr_grad_bf16_lds(LogregArgs a) {
   // half 1 hands its partial sums to half 0 through LDS (fixed order: half 0 + half 1);
   // a lane's four values of a tile are consecutive dims, moved as one 16-byte word
   f32x4 *red = reinterpret_cast<f32x4 *>(lds);
-  double *lred = reinterpret_cast<double *>(red + 4 * 2 * KC * 64);
+  double *lred = reinterpret_cast<double *>(red + 4 * 2 * 2 * KC * 64);
   if (rh == 1) {
 #pragma unroll
-    for (int dc = 0; dc < 2 * KC; ++dc) red[(cg * 2 * KC + dc) * 64 + lane] = gacc[dc];
-    lred[cg * 64 + lane] = lacc;
+    for (int g = 0; g < 2; ++g) {
+#pragma unroll
+      for (int dc = 0; dc < 2 * KC; ++dc) red[((pg * 2 + g) * 2 * KC + dc) * 64 + lane] = gacc[g][dc];
+      lred[(pg * 2 + g) * 64 + lane] = lacc[g];
+    }
   }
   __syncthreads();
   if (rh == 0) {
-    float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
-    if (mval) {
 #pragma unroll
-      for (int dc = 0; dc < 2 * KC; ++dc) {
-        const int64_t dd = 16 * dc + 4 * q;  // ld is a multiple of 8, so dd < ld covers dd .. dd + 3
-        if (dd < ld) {
-          const f32x4 v = gacc[dc] + red[(cg * 2 * KC + dc) * 64 + lane];
-          *reinterpret_cast<f32x4 *>(Gp + dd) = v;
+    for (int g = 0; g < 2; ++g) {
+      const int64_t m = mbase + 16 * g;
+      float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
+      if (m < N) {
+#pragma unroll
+        for (int dc = 0; dc < 2 * KC; ++dc) {
+          const int64_t dd = 16 * dc + 4 * q;  // ld is a multiple of 8, so dd < ld covers dd .. dd + 3
+          if (dd < ld) {
+            const f32x4 v = gacc[g][dc] + red[((pg * 2 + g) * 2 * KC + dc) * 64 + lane];
+            *reinterpret_cast<f32x4 *>(Gp + dd) = v;
+          }
         }
       }
-    }
-    lacc += lred[cg * 64 + lane];
-    lacc += __shfl_xor(lacc, 16);
-    lacc += __shfl_xor(lacc, 32);
-    if (mval && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// bf16 matrix-core gradient, direct-load variant for d > 128 (fragments
-// from L1/L2).  grid (ceil(N/64), S), 256 threads: wavefront w of workgroup
-// (gx, s) owns chains 64 gx + 16 w .. +15 and data blocks [s bps, (s+1) bps).
-// ---------------------------------------------------------------------------
-template <int KC>
-__global__ void __launch_bounds__(256) k_lr_grad_bf16_direct(LogregArgs a) {
-  if (!lr_gate(a)) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int q = lane >> 4, cl = lane & 15;
-  const int64_t N = a.N, ld = a.ld;
-  const int64_t m = ((int64_t)blockIdx.x * 4 + wave) * 16 + cl;
-  const bool mval = m < N;
-  const float *X = static_cast<const float *>(a.x);
-  // theta as the B operand: k slot 8q + j of chunk kc is coordinate 32kc + 16(j/4) + 4q + j%4
-  bf16x8 thi[KC], tlo[KC];
-#pragma unroll
-  for (int kc = 0; kc < KC; ++kc) {
-#pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-      const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (mval && d4 < ld) v = *reinterpret_cast<const float4 *>(X + m * ld + d4);
-      const float f[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const __bf16 hi = (__bf16)f[i];
-        thi[kc][4 * hh + i] = hi;
-        tlo[kc][4 * hh + i] = (__bf16)(f[i] - (float)hi);
-      }
+      double la = lacc[g] + lred[(pg * 2 + g) * 64 + lane];
+      la += __shfl_xor(la, 16);
+      la += __shfl_xor(la, 32);
+      // log2 units to natural log, with the sign of log p
+      if (m < N && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = -0.6931471805599453 * la;
     }
   }
-  f32x4 gacc[2 * KC];
-#pragma unroll
-  for (int dc = 0; dc < 2 * KC; ++dc) gacc[dc] = f32x4{0.f, 0.f, 0.f, 0.f};
-  double lacc = 0.0;
-  const LrOffsets off = logreg_layout(1, a.n, a.d, N, ld, a.S);
-  const bf16x8 *Xb = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xb);
-  const float *yf = reinterpret_cast<const float *>(a.scratch + off.yf);
-  const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
-  const int s = blockIdx.y;
-  const int b0 = s * a.bps;
-  const int b1 = (b0 + a.bps < a.NB) ? b0 + a.bps : a.NB;
-  const int64_t n = a.n;
-  for (int b = b0; b < b1; ++b) {
-    f32x4 z[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        const bf16x8 af = XF[(((int64_t)b * 2 + h) * KC + kc) * 64 + lane];
-        z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, thi[kc], z[h], 0, 0, 0);
-        z[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, tlo[kc], z[h], 0, 0, 0);
-      }
-    // epilogue (labels packed as ym = y - 1/2): r = y - sigmoid(z) =
-    // ym - copysign(1/(1 + e^{-|z|}) - 1/2, z), log p terms
-    // y z - softplus(z) = ym z - |z|/2 - log(1 + e^{-|z|})
-    bf16x8 rb;
-    float lsum = 0.f;
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t row = 32 * (int64_t)b + 16 * h + 4 * q + i;
-        const float zz = z[h][i];
-        const float ym = yf[row];
-        const float e = __expf(-fabsf(zz));
-        const float ope = 1.0f + e;
-        const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
-        const bool ok = row < n;
-        rb[4 * h + i] = (__bf16)(ok ? ym - copysignf(t, zz) : 0.f);
-        lsum += ok ? fmaf(ym, zz, -0.5f * fabsf(zz)) - __logf(ope) : 0.f;
-      }
-    lacc += (double)lsum;
-#pragma unroll
-    for (int dc = 0; dc < 2 * KC; ++dc) {
-      const bf16x8 ab = Xb[((int64_t)b * 2 * KC + dc) * 64 + lane];
-      gacc[dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, rb, gacc[dc], 0, 0, 0);
-    }
-  }
-  float *Gp = reinterpret_cast<float *>(a.scratch + off.Gp) + ((int64_t)s * N + m) * ld;
-  if (mval) {
-#pragma unroll
-    for (int dc = 0; dc < 2 * KC; ++dc)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t dd = 16 * dc + 4 * q + i;
-        if (dd < ld) Gp[dd] = gacc[dc][i];
-      }
-  }
-  lacc += __shfl_xor(lacc, 16);
-  lacc += __shfl_xor(lacc, 32);
-  if (mval && q == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
 }
 
 // ---------------------------------------------------------------------------
@@ -518,6 +476,28 @@ __device__ __forceinline__ void lr_grad_sum(const LogregArgs &a, const LrOffsets
   for (int i = 0; i < 8; ++i) g[0][i] = (e0 + i < a.d) ? acc[i] - (a.prior ? x[0][i] : Real(0)) : Real(0);
 }
 
+// The lane's share of the log-density terms that depend on theta alone: the
+// N(0, I) prior -|theta|^2 / 2 and, for the bf16 gradient (whose split sums
+// leave it out), sum_n (y_n - 1/2) z_n = theta . (X^T (y - 1/2)) in FP64.
+template <class Real>
+__device__ __forceinline__ double lr_theta_terms(const LogregArgs &a, const LrOffsets &off, int r,
+                                                 const Real (&x)[1][8]) {
+  double v = 0.0;
+  if (a.prior) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v -= 0.5 * (double)x[0][i] * (double)x[0][i];
+  }
+  if (a.wy_term) {
+    const int64_t e0 = 8 * (int64_t)r;
+    if (e0 < a.d) {
+      const double *wy = reinterpret_cast<const double *>(a.scratch + off.wy) + e0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v += (double)x[0][i] * wy[i];
+    }
+  }
+  return v;
+}
+
 template <class Real>
 __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   if (!lr_gate(a)) return;
@@ -550,13 +530,11 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     // log p and gradient at the caller's positions (a.x): split sums plus the prior
     double lps;
     lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
-    double v[1] = {0.0};
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[0] += (double)x[0][i] * (double)x[0][i];
+    double v[1] = {lr_theta_terms<Real>(a, off, r, x)};
     team_sum<1>(v, T, red, slot);
     if (act) {
       if (a.g_out) store_row<Real, 1>(static_cast<Real *>(a.g_out) + m * ld, r, T, d, g);
-      if (r == 0) a.logp_out[m] = lps - (a.prior ? 0.5 * v[0] : 0.0);
+      if (r == 0) a.logp_out[m] = lps + v[0];
     }
     return;
   }
@@ -573,15 +551,14 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
     if (mode == LR_INIT) {
       lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, 0, TAG_INIT_DIR, 0, z);
-      double v[3] = {0.0, 0.0, 0.0};
+      double v[3] = {lr_theta_terms<Real>(a, off, r, x), 0.0, 0.0};
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        v[0] += (double)x[0][i] * (double)x[0][i];
         v[1] += (double)g[0][i] * (double)g[0][i];
         v[2] += (double)z[0][i] * (double)z[0][i];
       }
       team_sum<3>(v, T, red, slot);
-      const double l1 = lps - (a.prior ? 0.5 * v[0] : 0.0);
+      const double l1 = lps + v[0];
       if (a.u0) {
         load_row<Real, 1>(static_cast<const Real *>(a.u0) + m * ld, r, T, d, act, u);
       } else {
@@ -606,15 +583,14 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     } else {
       const double Lm = H->L;
       const Real c1 = (Real)exp(-h / Lm), c2 = (Real)(sqrt(-expm1(-2.0 * h / Lm)) / sqrt((double)d));
-      double v[3] = {0.0, 0.0, 0.0};
+      double v[3] = {lr_theta_terms<Real>(a, off, r, x), 0.0, 0.0};
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        v[0] += (double)x[0][i] * (double)x[0][i];
         v[1] += (double)g[0][i] * (double)g[0][i];
         v[2] += (double)g[0][i] * (double)u[0][i];
       }
       team_sum<3>(v, T, red, slot);
-      const double l1 = lps - (a.prior ? 0.5 * v[0] : 0.0);
+      const double l1 = lps + v[0];
       const BMap b2 = b_map_dyn<Real>(a.dyn, v[1], v[2], h, dm1);
       lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, 0, z);
       double w1[1] = {0.0};
@@ -741,16 +717,15 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   load_row<Real, 1>(U + m * ld, r, T, d, act, u);
   double lps;
   lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[3] = {lr_theta_terms<Real>(a, off, r, x), 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const Real gt = sg[0][i] * g[0][i];
-    v[0] += (double)x[0][i] * (double)x[0][i];
     v[1] += (double)gt * (double)gt;
     v[2] += (double)gt * (double)u[0][i];
   }
   team_sum<3>(v, T, red, slot);
-  const double lnew = lps - (a.prior ? 0.5 * v[0] : 0.0);
+  const double lnew = lps + v[0];
   D = (act ? sc_D[m] + (sc_lprev[m] - lnew) : 0.0);
   lprev = lnew;
   const int k = a.k, j = a.j;
@@ -823,11 +798,12 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
 hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s) {
   const int KC = a.KC, NB = a.NB;
   const LrOffsets off = logreg_layout(1, a.n, a.d, a.N, a.ld, a.S);
-  const int64_t total = (int64_t)NB * 2 * KC * 64 * 2 + (int64_t)NB * 32;
+  const int64_t total = (int64_t)NB * 2 * KC * 64 * 2 + (int64_t)NB * 32 + a.ld;
   hipLaunchKernelGGL(k_lr_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                     static_cast<const unsigned short *>(a.X), a.y, a.n, a.d, KC, NB,
+                     static_cast<const unsigned short *>(a.X), a.y, a.n, a.d, a.ld, KC, NB,
                      reinterpret_cast<unsigned short *>(a.scratch + off.Xf),
-                     reinterpret_cast<unsigned short *>(a.scratch + off.Xb), reinterpret_cast<float *>(a.scratch + off.yf));
+                     reinterpret_cast<unsigned short *>(a.scratch + off.Xb), reinterpret_cast<float *>(a.scratch + off.yf),
+                     reinterpret_cast<double *>(a.scratch + off.wy));
   return hipGetLastError();
 }
 
@@ -838,29 +814,25 @@ hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_lr_grad_f64, grid, dim3(256), shm, s, a);
     return hipGetLastError();
   }
-  const dim3 grid((unsigned)((a.N + 63) / 64), (unsigned)a.S);
-  const size_t shm = (size_t)2 * (2 * 4 * a.KC * 64 + 16) * 16;
-  if (a.KC <= 4) {
-    void (*fn)(LogregArgs) = a.KC == 1 ? k_lr_grad_bf16_lds<1>
-                             : a.KC == 2 ? k_lr_grad_bf16_lds<2>
-                             : a.KC == 3 ? k_lr_grad_bf16_lds<3>
-                                         : k_lr_grad_bf16_lds<4>;
-    const hipError_t e = grant_lds(reinterpret_cast<const void *>(fn), shm);
-    if (e != hipSuccess) return e;
-    LogregArgs arg = a;
-    void *args[] = {&arg};
-    return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, dim3(512), args, shm, s);
-  }
-  switch (a.KC) {
-    case 5: hipLaunchKernelGGL(k_lr_grad_bf16_direct<5>, grid, dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL(k_lr_grad_bf16_direct<6>, grid, dim3(256), 0, s, a); break;
-    case 7: hipLaunchKernelGGL(k_lr_grad_bf16_direct<7>, grid, dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_lr_grad_bf16_direct<8>, grid, dim3(256), 0, s, a); break;
-    case 9: hipLaunchKernelGGL(k_lr_grad_bf16_direct<9>, grid, dim3(256), 0, s, a); break;
-    case 10: hipLaunchKernelGGL(k_lr_grad_bf16_direct<10>, grid, dim3(256), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (a.KC < 1 || a.KC > 4) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((a.N + 127) / 128), (unsigned)a.S);
+  // staging: two buffers of two blocks' fragments and labels; the final
+  // hand-over of half 1's partial sums reuses the same memory
+  const size_t stage = (size_t)2 * (2 * 4 * a.KC * 64 + 16) * 16;
+  const size_t red = (size_t)4 * 2 * 2 * a.KC * 64 * 16 + (size_t)4 * 2 * 64 * 8;
+  const size_t shm = stage > red ? stage : red;
+  // output tiles of 16 dims holding dims < d: 2 KC - 1 or 2 KC
+  const bool odd = (a.d + 15) / 16 < 2 * a.KC;
+  void (*const fns[4][2])(LogregArgs) = {{k_lr_grad_bf16_pair<1, 2>, k_lr_grad_bf16_pair<1, 1>},
+                                         {k_lr_grad_bf16_pair<2, 4>, k_lr_grad_bf16_pair<2, 3>},
+                                         {k_lr_grad_bf16_pair<3, 6>, k_lr_grad_bf16_pair<3, 5>},
+                                         {k_lr_grad_bf16_pair<4, 8>, k_lr_grad_bf16_pair<4, 7>}};
+  void (*fn)(LogregArgs) = fns[a.KC - 1][odd ? 1 : 0];
+  const hipError_t e = grant_lds(reinterpret_cast<const void *>(fn), shm);
+  if (e != hipSuccess) return e;
+  LogregArgs arg = a;
+  void *args[] = {&arg};
+  return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, dim3(512), args, shm, s);
 }
 
 hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, int block, size_t shmem, hipStream_t s) {
