@@ -33,11 +33,9 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int wgs, int &S, int &NB, int &bps) {
   (void)d;
   NB = (int)((n + 31) / 32);
-  // chain tiles of one gradient launch: 128 chains per bf16 workgroup; the
-  // FP64 kernel is split as if its tiles held 64 chains
-  const int64_t groups = prec != 0 ? (N + 127) / 128 : (N + 63) / 64;
-  // workgroups of one launch: one per CU
-  int64_t target = 256;
+  // chain tiles of one gradient launch: 64 chains per workgroup; two workgroups per CU
+  const int64_t groups = (N + 63) / 64;
+  int64_t target = 512;
   if (wgs > 0) target = wgs;
   int64_t want = target / (groups > 0 ? groups : 1);
   if (want < 1) want = 1;
@@ -107,16 +105,18 @@ __global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, i
 }
 
 // ---------------------------------------------------------------------------
-// bf16 matrix-core gradient (d <= 128).  grid (ceil(N/128), S), 512 threads =
-// 8 wavefronts: wavefront w owns the 32 chains of pair group w % 4 (two
-// 16-chain MFMA tiles, g = 0, 1) and row half w / 4 of the split's 32-row
+// bf16 matrix-core gradient (d <= 128).  grid (ceil(N/64), S), 256 threads =
+// 4 wavefronts: wavefront w owns the 32 chains of pair group w % 2 (two
+// 16-chain MFMA tiles, g = 0, 1) and row half w / 2 of the split's 32-row
 // blocks (half 0 takes even blocks, half 1 odd ones).  Each X fragment read
 // from LDS feeds both chain tiles, so LDS traffic per chain is half that of a
 // 16-chain wavefront.  The operand fragments of the next two blocks go from
 // global memory straight into LDS (global_load_lds_dwordx4: one wavefront
 // instruction writes 64 consecutive 16-byte fragments) while the current
 // ones are used; theta's hi and lo products accumulate into one register
-// tile.  One workgroup per CU (two wavefronts per SIMD, up to 256 VGPRs).
+// tile.  Two workgroups share a CU (two wavefronts per SIMD, up to 256
+// VGPRs each); they run independently, so one's matrix-core phase overlaps
+// the other's vector epilogue.
 //
 // The products carry z' = z log2(e) (theta is scaled before its hi/lo
 // split), so e^{-|z|} is one base-2 exponential.  With the packed label
@@ -192,19 +192,20 @@ __device__ __forceinline__ void lr_block_pair(const bf16x8 *L, const float *Y, i
 }
 
 template <int KC, int DT>
-__global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pair(LogregArgs a) {
+__global__ void __launch_bounds__(256, 2) k_lr_grad_bf16_pair(LogregArgs a) {
   if (!lr_gate(a)) return;
+  constexpr int kThr = 256;
   constexpr int kFrag = 4 * KC * 64;      // 16-byte fragments per 32-row block
-  constexpr int kPer = 2 * kFrag / 512;    // fragments per thread per iteration
+  constexpr int kPer = 2 * kFrag / kThr;   // fragments per thread per iteration
   constexpr int kBuf = 2 * kFrag + 16;     // one buffer: two blocks' fragments + their 2 x 32 labels
   constexpr int kBlk = 2 * KC * 64;        // forward (or backward) fragments of one block
   extern __shared__ bf16x8 lds[];          // [2 buffers][kBuf]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int pg = wave & 3, rh = wave >> 2;
+  const int pg = wave & 1, rh = wave >> 1;
   const int q = lane >> 4, cl = lane & 15;
   const int64_t N = a.N, ld = a.ld, n = a.n;
-  const int64_t mbase = (int64_t)blockIdx.x * 128 + pg * 32 + cl;  // chain of tile g: mbase + 16 g
+  const int64_t mbase = (int64_t)blockIdx.x * 64 + pg * 32 + cl;  // chain of tile g: mbase + 16 g
   const float *X = static_cast<const float *>(a.x);
   const LrOffsets off = logreg_layout(1, n, a.d, N, ld, a.S);
   const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
@@ -226,7 +227,7 @@ __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pair(LogregArgs a) {
   bool fwdk[kPer], usek[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    const int c = tid + 512 * k;
+    const int c = tid + kThr * k;
     const int half = c / kFrag, f = c - half * kFrag;
     halfk[k] = half;
     fwdk[k] = f < kBlk;
@@ -239,7 +240,7 @@ __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pair(LogregArgs a) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       if (usek[k] && b0 + 2 * it + halfk[k] < b1)
-        lds_dma16((fwdk[k] ? baseF : baseB) + step + offk[k], lds + buf * kBuf + 512 * k + 64 * wave);
+        lds_dma16((fwdk[k] ? baseF : baseB) + step + offk[k], lds + buf * kBuf + kThr * k + 64 * wave);
     }
     if (tid < 16) {
       const int64_t blk = b0 + 2 * it + (tid >> 3);
@@ -310,7 +311,7 @@ __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pair(LogregArgs a) {
   // half 1 hands its partial sums to half 0 through LDS (fixed order: half 0 + half 1);
   // a lane's four values of a tile are consecutive dims, moved as one 16-byte word
   f32x4 *red = reinterpret_cast<f32x4 *>(lds);
-  double *lred = reinterpret_cast<double *>(red + 4 * 2 * 2 * KC * 64);
+  double *lred = reinterpret_cast<double *>(red + 2 * 2 * 2 * KC * 64);
   if (rh == 1) {
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
@@ -345,90 +346,113 @@ __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pair(LogregArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// plain FP64 gradient.  grid (ceil(N/16), S), 256 threads, dynamic LDS holds
-// the 16 chains' theta and a 16 x 64 block of residuals.
+// plain FP64 gradient on the FP64 matrix cores (v_mfma_f64_16x16x4_f64).
+// grid (ceil(N/64), S), 256 threads = 4 wavefronts; wavefront w owns the 16
+// chains 64 bx + 16 w .. + 15, and the workgroup walks the split's rows in
+// tiles of 16, staged in LDS as FP64 rows (padded stride ld + 1 doubles).
+// Lane layout of the instruction (A 16 x 4, B 4 x 16, D 16 x 16): lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[l / 16 + 4 i]
+// [l % 16], i = 0..3.
+//   forward  z^T (rows x chains) += X[rows][k] theta[k][chains], 4 dims per
+//            instruction: lane l holds z of chain l % 16 for rows l/16 + 4i;
+//   epilogue r = y - sigmoid(z), y z - softplus(z) in FP64;
+//   backward G (chains x dims) += r^T[chains][rows] X[rows][dims]: K-step i
+//            takes rows i*4 .. i*4 + 3 as k = l / 16, exactly the rows the
+//            lane already holds, so r feeds the A operand from registers.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_lr_grad_f64(LogregArgs a) {
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int KS>  // KS = ceil(d / 4) input-dim steps; d <= 128
+__global__ void __launch_bounds__(256) k_lr_grad_f64_mfma(LogregArgs a) {
   if (!lr_gate(a)) return;
-  extern __shared__ double sm[];
+  constexpr int DT = (4 * KS + 15) / 16;  // output tiles of 16 dims
+  extern __shared__ double sm[];         // [2][16][ldl] rows, then [2][16] labels
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lo = lane & 15, hi = lane >> 4;
   const int64_t N = a.N, ld = a.ld, d = a.d, n = a.n;
-  double *th = sm;               // [16][ld]
-  double *R = sm + 16 * ld;      // [16][64]
-  const int tid = threadIdx.x;
-  const int64_t m0 = (int64_t)blockIdx.x * 16;
+  const int ldl = (int)ld + 1;
+  double *Xs = sm, *Ys = sm + 2 * 16 * ldl;
   const double *x = static_cast<const double *>(a.x);
   const double *X = static_cast<const double *>(a.X);
-  for (int64_t i = tid; i < 16 * ld; i += 256) {
-    const int64_t c = i / ld, e = i - c * ld;
-    th[i] = (m0 + c < N && e < d) ? x[(m0 + c) * ld + e] : 0.0;
+  const int64_t m = (int64_t)blockIdx.x * 64 + 16 * wave + lo;  // chain of the B operand / backward A operand
+  // theta as the forward B operand: step s supplies theta[m][4 s + hi]
+  double th[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int64_t e = 4 * k + hi;
+    th[k] = (m < N && e < d) ? x[m * ld + e] : 0.0;
   }
+  f64x4 gacc[DT];
+#pragma unroll
+  for (int t = 0; t < DT; ++t) gacc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double lacc = 0.0;
   const int s = blockIdx.y;
   const int64_t r0 = (int64_t)s * a.bps * 32;
   int64_t r1 = r0 + (int64_t)a.bps * 32;
   if (r1 > n) r1 = n;
-  // phase-1 role: one row, four chains; phase-2 role: one chain, coordinates dslot + 16k
-  const int prow = tid & 63, pc = (tid >> 6) * 4;
-  const int gc = tid >> 4, dslot = tid & 15;
-  const int kd = (int)((d + 15) / 16);
-  double G[20];
+  const int64_t ntile = (r1 - r0 + 15) / 16;
+  // staging of row tile tt into buffer b: 16 rows x ld doubles (zero past d and n), and the labels
+  auto stage = [&](int64_t tt, int b) {
+    const int64_t rb = r0 + 16 * tt;
+    for (int i = tid; i < 16 * (int)ld; i += 256) {
+      const int rr = i / (int)ld, e = i - rr * (int)ld;
+      const int64_t row = rb + rr;
+      Xs[(b * 16 + rr) * ldl + e] = (row < r1 && e < d) ? X[row * d + e] : 0.0;
+    }
+    if (tid < 16) Ys[b * 16 + tid] = (rb + tid < r1) ? a.y[rb + tid] : 0.0;
+  };
+  if (ntile > 0) stage(0, 0);
+  __syncthreads();
+  for (int64_t tt = 0; tt < ntile; ++tt) {
+    const int b = (int)(tt & 1);
+    if (tt + 1 < ntile) stage(tt + 1, b ^ 1);
+    const double *T = Xs + b * 16 * ldl;
+    // forward: A = X[row lo][4 k + hi]
+    f64x4 z = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < 20; ++k) G[k] = 0.0;
-  double lacc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t rb = r0; rb < r1; rb += 64) {
+    for (int k = 0; k < KS; ++k) z = __builtin_amdgcn_mfma_f64_16x16x4f64(T[lo * ldl + 4 * k + hi], th[k], z, 0, 0, 0);
+    // epilogue on the lane's rows hi + 4 i of chain m
+    const int64_t rb = r0 + 16 * tt;
+    double rv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = hi + 4 * i;
+      const double zz = z[i];
+      const double yv = Ys[b * 16 + rr];
+      const double ez = exp(-fabs(zz));
+      const double sg = (zz >= 0.0 ? 1.0 : ez) / (1.0 + ez);
+      const bool ok = rb + rr < r1;
+      rv[i] = ok ? yv - sg : 0.0;
+      lacc += ok ? yv * zz - (fmax(zz, 0.0) + log1p(ez)) : 0.0;
+    }
+    // backward: K-step i takes the rows hi + 4 i (A = r from registers, B = X[row][16 t + lo])
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double *Tr = T + (hi + 4 * i) * ldl;
+#pragma unroll
+      for (int t = 0; t < DT; ++t) {
+        const int e = 16 * t + lo;
+        gacc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv[i], e < ld ? Tr[e] : 0.0, gacc[t], 0, 0, 0);
+      }
+    }
     __syncthreads();
-    const int64_t row = rb + prow;
-    double z[4] = {0.0, 0.0, 0.0, 0.0};
-    if (row < r1) {
-      const double *xr = X + row * d;
-      for (int64_t e = 0; e < d; ++e) {
-        const double xv = xr[e];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) z[c] += xv * th[(pc + c) * ld + e];
-      }
-    }
-    const double yv = row < r1 ? a.y[row] : 0.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      double rr = 0.0;
-      if (row < r1) {
-        const double ez = exp(-fabs(z[c]));
-        const double sig = z[c] >= 0.0 ? 1.0 / (1.0 + ez) : ez / (1.0 + ez);
-        rr = yv - sig;
-        lacc[c] += yv * z[c] - (fmax(z[c], 0.0) + log1p(ez));
-      }
-      R[(pc + c) * 64 + prow] = rr;
-    }
-    __syncthreads();
-    const int64_t cnt = (r1 - rb) < 64 ? (r1 - rb) : 64;
-    for (int64_t rr = 0; rr < cnt; ++rr) {
-      const double rv = R[gc * 64 + rr];
-      const double *xr = X + (rb + rr) * d;
-#pragma unroll
-      for (int k = 0; k < 20; ++k) {
-        const int64_t e = dslot + 16 * k;
-        if (k < kd && e < d) G[k] += rv * xr[e];
-      }
-    }
   }
   const LrOffsets off = logreg_layout(0, n, d, N, ld, a.S);
   double *Gp = reinterpret_cast<double *>(a.scratch + off.Gp);
-  if (m0 + gc < N) {
+  // lane l holds G[chain 16 w + hi + 4 i][dim 16 t + lo]
 #pragma unroll
-    for (int k = 0; k < 20; ++k) {
-      const int64_t e = dslot + 16 * k;
-      if (k < kd && e < ld) Gp[((int64_t)s * N + m0 + gc) * ld + e] = G[k];
+  for (int t = 0; t < DT; ++t) {
+    const int64_t e = 16 * t + lo;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t mc = (int64_t)blockIdx.x * 64 + 16 * wave + hi + 4 * i;
+      if (mc < N && e < ld) Gp[((int64_t)s * N + mc) * ld + e] = gacc[t][i];
     }
   }
-  // log p partials: the 64 lanes of a wavefront share the same four chains
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int msk = 32; msk >= 1; msk >>= 1) lacc[c] += __shfl_xor(lacc[c], msk);
-  if ((tid & 63) == 0) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (m0 + pc + c < N) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m0 + pc + c] = lacc[c];
-  }
+  // log p partial of chain m: the lanes with equal lo hold its rows (xor over hi)
+  lacc += __shfl_xor(lacc, 16);
+  lacc += __shfl_xor(lacc, 32);
+  if (m < N && hi == 0) reinterpret_cast<double *>(a.scratch + off.lp)[(int64_t)s * N + m] = lacc;
 }
 
 // ---------------------------------------------------------------------------
@@ -809,17 +833,29 @@ hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s) {
 
 hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
   if (prec == 0) {
-    const dim3 grid((unsigned)((a.N + 15) / 16), (unsigned)a.S);
-    const size_t shm = (size_t)(16 * a.ld + 16 * 64) * sizeof(double);
-    hipLaunchKernelGGL(k_lr_grad_f64, grid, dim3(256), shm, s, a);
+    const int KS = (int)((a.d + 3) / 4);
+    if (KS < 1 || KS > 32) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((a.N + 63) / 64), (unsigned)a.S);
+    const size_t shm = ((size_t)2 * 16 * (a.ld + 1) + 32) * sizeof(double);
+    typedef void (*Fn)(LogregArgs);
+    static const Fn fns[32] = {
+        k_lr_grad_f64_mfma<1>,  k_lr_grad_f64_mfma<2>,  k_lr_grad_f64_mfma<3>,  k_lr_grad_f64_mfma<4>,
+        k_lr_grad_f64_mfma<5>,  k_lr_grad_f64_mfma<6>,  k_lr_grad_f64_mfma<7>,  k_lr_grad_f64_mfma<8>,
+        k_lr_grad_f64_mfma<9>,  k_lr_grad_f64_mfma<10>, k_lr_grad_f64_mfma<11>, k_lr_grad_f64_mfma<12>,
+        k_lr_grad_f64_mfma<13>, k_lr_grad_f64_mfma<14>, k_lr_grad_f64_mfma<15>, k_lr_grad_f64_mfma<16>,
+        k_lr_grad_f64_mfma<17>, k_lr_grad_f64_mfma<18>, k_lr_grad_f64_mfma<19>, k_lr_grad_f64_mfma<20>,
+        k_lr_grad_f64_mfma<21>, k_lr_grad_f64_mfma<22>, k_lr_grad_f64_mfma<23>, k_lr_grad_f64_mfma<24>,
+        k_lr_grad_f64_mfma<25>, k_lr_grad_f64_mfma<26>, k_lr_grad_f64_mfma<27>, k_lr_grad_f64_mfma<28>,
+        k_lr_grad_f64_mfma<29>, k_lr_grad_f64_mfma<30>, k_lr_grad_f64_mfma<31>, k_lr_grad_f64_mfma<32>};
+    hipLaunchKernelGGL(fns[KS - 1], grid, dim3(256), shm, s, a);
     return hipGetLastError();
   }
   if (a.KC < 1 || a.KC > 4) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((a.N + 127) / 128), (unsigned)a.S);
+  const dim3 grid((unsigned)((a.N + 63) / 64), (unsigned)a.S);
   // staging: two buffers of two blocks' fragments and labels; the final
   // hand-over of half 1's partial sums reuses the same memory
   const size_t stage = (size_t)2 * (2 * 4 * a.KC * 64 + 16) * 16;
-  const size_t red = (size_t)4 * 2 * 2 * a.KC * 64 * 16 + (size_t)4 * 2 * 64 * 8;
+  const size_t red = (size_t)2 * 2 * 2 * a.KC * 64 * 16 + (size_t)2 * 2 * 64 * 8;
   const size_t shm = stage > red ? stage : red;
   // output tiles of 16 dims holding dims < d: 2 KC - 1 or 2 KC
   const bool odd = (a.d + 15) / 16 < 2 * a.KC;
@@ -832,7 +868,7 @@ hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
   if (e != hipSuccess) return e;
   LogregArgs arg = a;
   void *args[] = {&arg};
-  return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, dim3(512), args, shm, s);
+  return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, dim3(256), args, shm, s);
 }
 
 hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, int block, size_t shmem, hipStream_t s) {
