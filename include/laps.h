@@ -211,6 +211,21 @@ laps_status laps_workspace_size(const laps_config *cfg, const laps_target *targe
 laps_status laps_init(const laps_config *cfg, const laps_target *target, void *x_dev, const void *u0_dev,
                       void *ws_dev, size_t ws_bytes, void *stream, laps_ctx **out);
 
+/* laps_init for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * initialisation with the workspace taken from a static device array of the
+ * library, 32 MiB per device, held until the process ends (enough for the
+ * 4096-chain logistic-regression workload, 23.6 MiB).  Calls no allocating
+ * routine.  Configurations whose laps_workspace_size exceeds 32 MiB return
+ * LAPS_EWORKSPACE.  The context is library storage, one per device:
+ * laps_destroy leaves it in place, and a later laps_init_static on the same
+ * device reuses the array and the context, so the earlier static context is
+ * then invalid.  Steps of two static contexts cannot overlap on one device
+ * (they would race on the array); workspace contents left by an earlier call
+ * are cleared or rewritten by the initialisation exactly as in laps_init. */
+laps_status laps_init_static(const laps_config *cfg, const laps_target *target, void *x_dev, const void *u0_dev,
+                             void *stream, laps_ctx **out);
+
 /* Enqueues up to n_steps unadjusted MCLMC steps (eq. discrete update with the
  * leapfrog integrator, Appendix D) each followed by the ensemble statistics
  * and the unadjusted controller (section "Unadjusted initialization", eq.

@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -30,6 +31,7 @@ struct laps_ctx {
   int integ;
   bool adj_started;
   bool packed_ok;  // logistic regression: operand fragments of X packed
+  bool is_static = false;  // context of laps_init_static: library storage, never deleted
   // workspace
   DevHyper *hyp;
   void *u, *g, *sigma, *aux, *packed;
@@ -558,31 +560,34 @@ extern "C" laps_status laps_workspace_size(const laps_config *cfg, const laps_ta
   return LAPS_OK;
 }
 
-extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, void *x_dev, const void *u0_dev,
-                                 void *ws_dev, size_t ws_bytes, void *stream, laps_ctx **out) {
+namespace {
+
+// Arguments checked before any device call: configuration, pointers and
+// their alignment; fills the launch shape and workspace layout.
+laps_status check_init(const laps_config *cfg, const laps_target *tg, const void *x_dev, const void *u0_dev,
+                       laps_ctx **out, Shape &s, Layout &L) {
   std::string why;
   laps_status st = validate(cfg, tg, why);
   if (st != LAPS_OK) {
     g_last_global = why;
     return st;
   }
-  if (!x_dev || !ws_dev || !out) {
+  if (!x_dev || !out) {
     g_last_global = "null pointer argument";
     return LAPS_EINVAL;
   }
-  if (((uintptr_t)x_dev & 31) || ((uintptr_t)ws_dev & 255) || (u0_dev && ((uintptr_t)u0_dev & 31))) {
-    g_last_global = "misaligned pointer (x/u0 need 32 bytes, workspace 256)";
+  if (((uintptr_t)x_dev & 31) || (u0_dev && ((uintptr_t)u0_dev & 31))) {
+    g_last_global = "misaligned pointer (x/u0 need 32 bytes)";
     return LAPS_EINVAL;
   }
-  Shape s;
   shape_for(cfg, tg, s);
-  const Layout L = layout(cfg, tg, s);
-  if (ws_bytes < L.total) {
-    g_last_global = "workspace too small";
-    return LAPS_EWORKSPACE;
-  }
-  laps_ctx *c = new (std::nothrow) laps_ctx();
-  if (!c) return LAPS_EINVAL;
+  L = layout(cfg, tg, s);
+  return LAPS_OK;
+}
+
+// Carves the workspace w for context c and enqueues the initialisation.
+laps_status init_into(laps_ctx *c, const laps_config *cfg, const laps_target *tg, void *x_dev, const void *u0_dev,
+                      char *w, const Shape &s, const Layout &L, void *stream) {
   c->cfg = *cfg;
   c->tg = *tg;
   c->x = x_dev;
@@ -604,7 +609,6 @@ extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, 
   c->integ = integ_for(cfg);
   c->adj_started = false;
   c->packed_ok = false;
-  char *w = static_cast<char *>(ws_dev);
   c->hyp = reinterpret_cast<DevHyper *>(w + L.hyp);
   c->u = w + L.u;
   c->g = w + L.g;
@@ -630,26 +634,107 @@ extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, 
   hipError_t e;
   if ((e = hipMemsetAsync(c->shiftK, 0, (size_t)c->ld * 8, c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(c->u, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess ||
-      (e = hipMemsetAsync(c->g, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess) {
-    fail(c, e, "workspace clear");
-    delete c;
-    return LAPS_EDEVICE;
-  }
+      (e = hipMemsetAsync(c->g, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess)
+    return fail(c, e, "workspace clear");
   if (tg->kind == LAPS_GAUSS_DIAG || tg->kind == LAPS_STOCHVOL)
     e = launch_prep_aux(tg->kind, c->dbl, tg->data[0], c->aux, cfg->d, c->ld, c->stream);
   if (e == hipSuccess) e = launch_hyper_init(ca, c->stream);
-  if (e != hipSuccess) {
-    fail(c, e, "init");
-    delete c;
-    return LAPS_EDEVICE;
-  }
-  st = enqueue_chain_kernel(c, KK_INIT, u0_dev);
+  if (e != hipSuccess) return fail(c, e, "init");
+  laps_status st = enqueue_chain_kernel(c, KK_INIT, u0_dev);
   if (st == LAPS_OK && (e = launch_finalize(ca, FIN_INIT, c->stream)) != hipSuccess) st = fail(c, e, "finalize");
   if (st == LAPS_OK && (e = launch_ctl_init(ca, c->stream)) != hipSuccess) st = fail(c, e, "controller init");
+  return st;
+}
+
+}  // namespace
+
+extern "C" laps_status laps_init(const laps_config *cfg, const laps_target *tg, void *x_dev, const void *u0_dev,
+                                 void *ws_dev, size_t ws_bytes, void *stream, laps_ctx **out) {
+  Shape s;
+  Layout L;
+  laps_status st = check_init(cfg, tg, x_dev, u0_dev, out, s, L);
+  if (st != LAPS_OK) return st;
+  if (!ws_dev) {
+    g_last_global = "null pointer argument";
+    return LAPS_EINVAL;
+  }
+  if ((uintptr_t)ws_dev & 255) {
+    g_last_global = "misaligned pointer (workspace needs 256 bytes)";
+    return LAPS_EINVAL;
+  }
+  if (ws_bytes < L.total) {
+    g_last_global = "workspace too small";
+    return LAPS_EWORKSPACE;
+  }
+  laps_ctx *c = new (std::nothrow) laps_ctx();
+  if (!c) return LAPS_EINVAL;
+  st = init_into(c, cfg, tg, x_dev, u0_dev, static_cast<char *>(ws_dev), s, L, stream);
   if (st != LAPS_OK) {
     delete c;
     return st;
   }
+  *out = c;
+  return LAPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation without allocation, for callers that cannot allocate device
+// memory.  The workspace is `laps_static_scratch`, a file-scope device array
+// that every GPU the library runs on holds until the process ends; host code
+// uses only the address that hipGetSymbolAddress returns for it on each
+// device (kept per device), never the array's name.  The context itself is
+// library storage, one per device.  A later laps_init_static on the same
+// device reuses both, so the previous static context of that device is then
+// invalid; calls that overlap on one device race.
+//
+// The array has external linkage: a `static` device array stays a local
+// symbol of the device code object (absent from its dynamic symbol table),
+// which the runtime cannot resolve by name.  Its start is rounded up to 256
+// bytes inside 256 bytes of slack, whatever alignment the loader gives it.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticWorkspaceBytes = (size_t)32 << 20;
+constexpr int kStaticDevices = 64;
+__device__ __align__(256) unsigned char laps_static_scratch[kStaticWorkspaceBytes + 256];
+static void *g_scratch_ptr[kStaticDevices];
+static laps_ctx g_static_ctx[kStaticDevices];
+static std::mutex g_static_mu;
+
+extern "C" laps_status laps_init_static(const laps_config *cfg, const laps_target *tg, void *x_dev,
+                                        const void *u0_dev, void *stream, laps_ctx **out) {
+  Shape s;
+  Layout L;
+  laps_status st = check_init(cfg, tg, x_dev, u0_dev, out, s, L);
+  if (st != LAPS_OK) return st;
+  if (L.total > kStaticWorkspaceBytes) {
+    g_last_global = "the configuration needs " + std::to_string(L.total) + " workspace bytes; the static workspace of "
+                    "laps_init_static holds " + std::to_string(kStaticWorkspaceBytes);
+    return LAPS_EWORKSPACE;
+  }
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, e, "current device");
+  if (dev < 0 || dev >= kStaticDevices) {
+    g_last_global = "device index beyond the static contexts";
+    return LAPS_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(laps_static_scratch));
+    if (e != hipSuccess || !p) return fail(nullptr, e != hipSuccess ? e : hipErrorInvalidSymbol, "static workspace");
+    g_scratch_ptr[dev] = reinterpret_cast<void *>(((uintptr_t)p + 255) & ~(uintptr_t)255);
+  }
+  laps_ctx *c = &g_static_ctx[dev];
+  for (hipEvent_t v : c->log_ev) hipEventDestroy(v);
+  c->log_ev.clear();
+  c->log_which = 0;
+  c->log_every = 1;
+  c->log_seen = 0;
+  c->log_used = 0;
+  c->err.clear();
+  c->is_static = true;
+  st = init_into(c, cfg, tg, x_dev, u0_dev, static_cast<char *>(g_scratch_ptr[dev]), s, L, stream);
+  if (st != LAPS_OK) return st;
   *out = c;
   return LAPS_OK;
 }
@@ -932,6 +1017,7 @@ extern "C" void *laps_buffer(laps_ctx *c, int32_t which) {
 }
 
 extern "C" laps_status laps_destroy(laps_ctx *c) {
+  if (c && c->is_static) return LAPS_OK;  // library storage, reused by the next laps_init_static
   delete c;
   return LAPS_OK;
 }

@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
                 ("sum_var", ctypes.c_double)]
 
 
-EXPORTS = ["laps_config_default", "laps_row_stride", "laps_workspace_size", "laps_init", "laps_step_unadjusted",
+EXPORTS = ["laps_config_default", "laps_row_stride", "laps_workspace_size", "laps_init", "laps_init_static",
+           "laps_step_unadjusted",
            "laps_step_adjusted", "laps_ensemble_stats", "laps_target_eval", "laps_eval", "laps_philox_words",
            "laps_philox_normals", "laps_time_gradient", "laps_time_kernel", "laps_kernel_log",
            "laps_kernel_log_read", "laps_restart", "laps_graph_create",
@@ -90,6 +91,7 @@ def lib():
         "laps_row_stride": (I64, [I64]),
         "laps_workspace_size": (I32, [P, P, P]),
         "laps_init": (I32, [P, P, P, P, P, ctypes.c_size_t, P, P]),
+        "laps_init_static": (I32, [P, P, P, P, P, P]),
         "laps_step_unadjusted": (I32, [P, I64]),
         "laps_step_adjusted": (I32, [P, I64]),
         "laps_ensemble_stats": (I32, [P, P, P]),
@@ -257,7 +259,8 @@ class Sampler:
     w: workload dict (see workloads.py); x0: [N, d] initial positions.
     cfg keywords override the paper's defaults (laps_config fields)."""
 
-    def __init__(self, w: dict, prec="f64", x0=None, seed=None, device="cuda:0", u0=None, **cfg):
+    def __init__(self, w: dict, prec="f64", x0=None, seed=None, device="cuda:0", u0=None, static_workspace=False,
+                 **cfg):
         torch = _torch()
         self.prec = PRECISIONS[prec]
         self.target = Target(w, self.prec, device)
@@ -284,17 +287,24 @@ class Sampler:
         nbytes = ctypes.c_size_t(0)
         _check(lib().laps_workspace_size(ctypes.byref(c), ctypes.byref(self.target.s), ctypes.byref(nbytes)))
         self.ws_bytes = nbytes.value
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        # static_workspace: laps_init_static, the library's own device array (no workspace tensor)
+        self.static_workspace = bool(static_workspace)
+        self.ws = None if self.static_workspace else torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         if self.target.kind == CALLBACK:
-            self.target.buffers += [self.x, self.ws]
+            self.target.buffers += [t for t in (self.x, self.ws) if t is not None]
         self.per_dim = torch.empty((4, d), dtype=torch.float64, device=device)
         self.ctx = ctypes.c_void_p()
         self._init()
 
     def _init(self):
-        st = lib().laps_init(ctypes.byref(self.cfg), ctypes.byref(self.target.s), ctypes.c_void_p(self.x.data_ptr()),
-                             ctypes.c_void_p(self.u0.data_ptr()) if self.u0 is not None else None,
-                             ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, _stream_ptr(), ctypes.byref(self.ctx))
+        u0 = ctypes.c_void_p(self.u0.data_ptr()) if self.u0 is not None else None
+        if self.static_workspace:
+            st = lib().laps_init_static(ctypes.byref(self.cfg), ctypes.byref(self.target.s),
+                                        ctypes.c_void_p(self.x.data_ptr()), u0, _stream_ptr(), ctypes.byref(self.ctx))
+        else:
+            st = lib().laps_init(ctypes.byref(self.cfg), ctypes.byref(self.target.s), ctypes.c_void_p(self.x.data_ptr()),
+                                 u0, ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, _stream_ptr(),
+                                 ctypes.byref(self.ctx))
         _check(st)
 
     def reinit(self, x0):
@@ -395,6 +405,8 @@ class Sampler:
     def buffer(self, name: str):
         """Views of workspace arrays: u, g ([N, d]), logp, delta, acc ([N]), sigma ([d])."""
         torch = _torch()
+        if self.ws is None:
+            raise LapsError(EUNSUPPORTED, "buffer views need a caller workspace (not static_workspace)")
         idx = {"u": 0, "g": 1, "logp": 2, "delta": 3, "acc": 4, "sigma": 5}[name]
         ptr = lib().laps_buffer(self.ctx, idx)
         off = ptr - self.ws.data_ptr()

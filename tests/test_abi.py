@@ -241,3 +241,22 @@ def test_dimension_limits(L):
         c, t = _cfg_target(L, kind=0, N=4, d=bad_d)
         c.prec = prec
         assert _ws(L, c, t)[0] != L.OK
+
+
+def test_static_init_refuses_oversized_workspace_before_touching_the_device(L):
+    """laps_init_static validates like laps_init and refuses configurations
+    whose workspace exceeds its static array (32 MiB) with LAPS_EWORKSPACE,
+    before any device call."""
+    c, t = _cfg_target(L, kind=2, N=4096, d=2429)
+    c.prec = L.F32
+    st, n = _ws(L, c, t)
+    assert st == L.OK and n > 32 << 20
+    x = ctypes.c_void_p(0x100000)
+    ctx = ctypes.c_void_p()
+    assert L.lib().laps_init_static(ctypes.byref(c), ctypes.byref(t), x, None, None, ctypes.byref(ctx)) == L.EWORKSPACE
+    assert b"static workspace" in L.lib().laps_last_error(None)
+    c, t = _cfg_target(L, kind=0, N=1, d=10)
+    assert L.lib().laps_init_static(ctypes.byref(c), ctypes.byref(t), x, None, None, ctypes.byref(ctx)) == L.EINVAL
+    c, t = _cfg_target(L, kind=0, N=16, d=10)
+    assert L.lib().laps_init_static(ctypes.byref(c), ctypes.byref(t), ctypes.c_void_p(0x100004), None, None,
+                                    ctypes.byref(ctx)) == L.EINVAL
