@@ -54,3 +54,38 @@ def test_stochvol_reference_is_stationary_and_precise():
     assert np.all(e > 0) and np.all(v > 0)
     assert r["halves_z_max"] < 4.5 and 0.4 < r["halves_z_median"] < 0.9
     assert r["max_se_over_std"] < 0.05
+
+
+def test_phi4_reference_is_stationary_and_precise():
+    """The phi^4 reference (tests/golden/phi4_moments.py, FP64 oracle, all
+    sites pooled): one value for every site, the eight ensembles agree within
+    their spread, the two halves of the pooled window agree, and the
+    reference's own noise is far below the bias threshold it is used
+    against."""
+    r = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "phi4_L64_moments.json")))
+    e, v = np.array(r["E_x2"]), np.array(r["Var_x2"])
+    assert e.shape == (64 * 64,) and np.all(e == e[0]) and np.all(v == v[0]) and v[0] > 0
+    assert r["se_over_std"] < 0.01 and r["halves_z"] < 4
+    pe = np.array(r["per_ensemble"])
+    assert np.max(np.abs(pe - e[0])) < 6 * r["se_E_site"] * np.sqrt(len(pe))
+    # the double well's minima lie at phi^2 = -m^2 / (4 lambda) = 1/8; the site average is near them
+    assert abs(e[0] - 0.125) < 0.02
+
+
+def test_stochvol_laplace_reference_against_sampler_ensembles():
+    """The stochastic-volatility references: the Laplace-method one (no
+    sampler, tests/golden/stochvol_laplace.py) and the FP64 oracle's
+    128-chain ensembles (tests/golden/stochvol_moments.py).  The latent
+    log-volatilities agree (median b^2 between them ~1e-3), while the
+    hyperparameters s and r differ by 8-10 of the ensembles' own standard
+    errors: the ensembles, 300 transitions long, have not converged in the
+    slow direction s.  The Laplace value lies within the bias threshold of
+    the 4096-chain GPU ensembles' long-run E[s^2] ~ 7.6."""
+    la = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "stochvol_T2427_laplace.json")))
+    en = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "stochvol_T2427_moments.json")))
+    e, v, eo = np.array(la["E_x2"]), np.array(la["Var_x2"]), np.array(en["E_x2"])
+    T = 2427
+    b2 = (eo - e) ** 2 / v
+    assert np.median(b2[:T]) < 3e-3 and la["grid_edge_mass"] < 1e-4
+    assert b2[T] > 0.03  # s: the ensembles' value is off
+    assert (7.6 - e[T]) ** 2 / v[T] < 0.01
