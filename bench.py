@@ -25,7 +25,10 @@ time_to_bias: wall-clock and gradients per chain until the squared bias of
 the second moments b^2_max first drops below 0.01 on the diagonal Gaussian
 (closed-form moments), FP64 and FP32 state; the same on the rotated
 ill-conditioned Gaussian, and on the logistic-regression posterior (bf16 and
-plain FP64 GPU paths, reference moments from the FP64 oracle).
+plain FP64 GPU paths, reference moments from the FP64 oracle); with
+--workload stochvol or phi4, on those posteriors in FP32 and FP64 state
+(reference moments from the Laplace method over the hyperparameter grid, and
+from the FP64 oracle).
 cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload.
 f64_gpu: the same run with the plain FP64 path.
 """
@@ -49,7 +52,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the bf16 gradient kernel on the logistic-regression workload, from FETCH_SIZE
 # and WRITE_SIZE counters scaled by what they read for a plain copy of known size; kept with the counter
 # summary under profiles/ and reset to None whenever the kernel changes.
-LR_GRAD_TRAFFIC_BYTES = None
+LR_GRAD_TRAFFIC_BYTES = 35.09e6
 N_UNADJ, N_ADJ = 1000, 67
 # the dominant kernel's launches bracketed by HIP events inside the timed runs: one in LOG_EVERY
 LOG_EVERY = int(os.environ.get("LAPS_BENCH_LOG_EVERY", "10"))
@@ -155,13 +158,16 @@ def cpu_baseline(w, n_chains=256, n_unadj=10, n_adj=1):
 def _bias_reference(target):
     """Workload and the exact E[x_i^2], Var[x_i^2] of its target: closed forms
     for the two Gaussians (zero mean: E = s2, Var = 2 s2^2), the FP64
-    oracle's reference moments for logistic regression and stochastic
-    volatility."""
+    oracle's reference moments for logistic regression, and the Laplace-method
+    reference (oracle/sv_laplace.py, no sampler involved) for stochastic
+    volatility, and the FP64 oracle's site-pooled reference for phi^4 (every
+    site alike by translation invariance)."""
     from paper_2601_16696_amd import workloads
-    if target in ("logreg", "stochvol"):
-        name = "logreg_n5000_d100_moments.json" if target == "logreg" else "stochvol_T2427_moments.json"
+    if target in ("logreg", "stochvol", "phi4"):
+        name = {"logreg": "logreg_n5000_d100_moments.json", "stochvol": "stochvol_T2427_laplace.json",
+                "phi4": "phi4_L64_moments.json"}[target]
         ref = json.load(open(os.path.join(ROOT, "tests", "golden", name)))
-        w = workloads.logreg() if target == "logreg" else workloads.stochvol()
+        w = getattr(workloads, target)()
         return w, np.array(ref["E_x2"]), np.array(ref["Var_x2"])
     w = workloads.gaussian() if target == "gauss" else workloads.ill_gaussian()
     s2 = np.asarray(w["sigma2"] if target == "gauss" else w["cov_diag"])
@@ -274,7 +280,7 @@ def main():
         roof = {"bound": "mfma" if prec == "bf16" else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": LR_GRAD_TRAFFIC_BYTES if prec == "bf16" else None,
                 "traffic_unit": "bytes per launch",
-                "kernel": "k_lr_grad_bf16_pair<4, 7>" if prec == "bf16" else "k_lr_grad_f64", "kernel_ms": kern["ms"],
+                "kernel": "k_lr_grad_bf16_pipe<4, 7>" if prec == "bf16" else "k_lr_grad_f64", "kernel_ms": kern["ms"],
                 "launches_timed": kern["launches"], "isolated_kernel_ms": r["grad_ms"],
                 "algorithmic_flops_per_launch": work}
         precision = ("bf16 matrix-core gradient, fp32 state, fp64 energy error and reductions"
@@ -334,7 +340,7 @@ def main():
         line["f64_gpu"] = {"value": r64["value"], "ms_per_step": r64["ms"], "gradient_ms": r64["grad_ms"],
                            "speedup_of_mixed": line["value"] / r64["value"]}
         del r64["sampler"]
-    if not args.no_bias:
+    if not args.no_bias and args.workload == "logreg":
         line["time_to_bias"] = {"workload": "gaussian_diag_d100_N1024 (closed-form moments), automatic switch",
                                 "criterion": "first step with b2_max < 0.01",
                                 "f64": time_to_bias("f64"), "f32": time_to_bias("f32")}
@@ -350,7 +356,24 @@ def main():
                         "(8 x 64 chains, 60 pooled MAMS transitions each; tests/golden/logreg_n5000_d100_moments.json)",
             "criterion": "first step with b2_max < 0.01",
             "bf16": lb, "f64": l64,
-            "speedup_of_mixed": (l64["ms"] / lb["ms"]) if lb.get("ms") and l64.get("ms") else None}
+            "speedup_of_mixed": (l64["ms"] / lb["ms"]) if lb.get("ms") and l64.get("ms") else None,
+            "grads_per_chain_at_crossing": {"bf16": lb.get("grads_per_chain"), "f64": l64.get("grads_per_chain")}}
+    if not args.no_bias and args.workload == "stochvol":
+        l32 = time_to_bias("f32", target="stochvol", n_adj=400)
+        l64 = time_to_bias("f64", target="stochvol", n_adj=400)
+        line["time_to_bias_stochvol"] = {
+            "workload": "stochvol_T2427_N4096, automatic switch; E_p[x_i^2] and Var_p[x_i^2] from the Laplace method "
+                        "over a (s, r) grid (oracle/sv_laplace.py; tests/golden/stochvol_T2427_laplace.json)",
+            "criterion": "first step with b2_max < 0.01", "paper_laps_grads_context": 1325,
+            "f32": l32, "f64": l64,
+            "speedup_of_f32": (l64["ms"] / l32["ms"]) if l32.get("ms") and l64.get("ms") else None}
+    if not args.no_bias and args.workload == "phi4":
+        l32, l64 = time_to_bias("f32", target="phi4"), time_to_bias("f64", target="phi4")
+        line["time_to_bias_phi4"] = {
+            "workload": "phi4_L64_N2048, automatic switch; E_p[x_i^2] and Var_p[x_i^2] from the FP64 oracle, all sites "
+                        "pooled (tests/golden/phi4_L64_moments.json)",
+            "criterion": "first step with b2_max < 0.01", "f32": l32, "f64": l64,
+            "speedup_of_f32": (l64["ms"] / l32["ms"]) if l32.get("ms") and l64.get("ms") else None}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, **CPU_SAMPLE[args.workload])
     print(json.dumps(line))

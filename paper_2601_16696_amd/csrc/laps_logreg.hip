@@ -33,9 +33,10 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int wgs, int &S, int &NB, int &bps) {
   (void)d;
   NB = (int)((n + 31) / 32);
-  // chain tiles of one gradient launch: 64 chains per workgroup; two workgroups per CU
-  const int64_t groups = (N + 63) / 64;
-  int64_t target = 512;
+  // chain tiles of one gradient launch: 128 chains per bf16 workgroup (one per
+  // CU), 64 per FP64 one (two per CU)
+  const int64_t groups = prec != 0 ? (N + 127) / 128 : (N + 63) / 64;
+  int64_t target = prec != 0 ? 256 : 512;
   if (wgs > 0) target = wgs;
   int64_t want = target / (groups > 0 ? groups : 1);
   if (want < 1) want = 1;
@@ -105,18 +106,24 @@ __global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, i
 }
 
 // ---------------------------------------------------------------------------
-// bf16 matrix-core gradient (d <= 128).  grid (ceil(N/64), S), 256 threads =
-// 4 wavefronts: wavefront w owns the 32 chains of pair group w % 2 (two
-// 16-chain MFMA tiles, g = 0, 1) and row half w / 2 of the split's 32-row
-// blocks (half 0 takes even blocks, half 1 odd ones).  Each X fragment read
-// from LDS feeds both chain tiles, so LDS traffic per chain is half that of a
-// 16-chain wavefront.  The operand fragments of the next two blocks go from
-// global memory straight into LDS (global_load_lds_dwordx4: one wavefront
-// instruction writes 64 consecutive 16-byte fragments) while the current
-// ones are used; theta's hi and lo products accumulate into one register
-// tile.  Two workgroups share a CU (two wavefronts per SIMD, up to 256
-// VGPRs each); they run independently, so one's matrix-core phase overlaps
-// the other's vector epilogue.
+// bf16 matrix-core gradient (d <= 128).  grid (ceil(N/128), S), 512 threads =
+// 8 wavefronts, one workgroup per CU: wavefront w owns the 32 chains of pair
+// group w % 4 (two 16-chain MFMA tiles, g = 0, 1) and row half w / 4 of the
+// split's 32-row blocks (half 0 takes even blocks, half 1 odd ones), so each
+// X fragment read from LDS feeds both chain tiles.
+//
+// Software pipeline.  Iteration it uses the blocks staged for it (its
+// epilogue and backward product) and for it + 1 (the forward product of the
+// wavefront's next block), while the blocks of it + 2 travel from global
+// memory straight into LDS (global_load_lds_dwordx4: one wavefront
+// instruction writes 64 consecutive 16-byte fragments).  Three LDS buffers
+// rotate as separate arrays with the rotation unrolled, so that the compiler
+// can see that a DMA into one buffer does not alias reads of the others and
+// waits for it only at the iteration's barrier.  Within an iteration the
+// forward products of the next block are independent of the current block's
+// sigmoid/softplus epilogue, so the matrix cores and the vector ALU of a
+// wavefront work at the same time.  theta's hi and lo products accumulate
+// into one register tile.
 //
 // The products carry z' = z log2(e) (theta is scaled before its hi/lo
 // split), so e^{-|z|} is one base-2 exponential.  With the packed label
@@ -136,11 +143,11 @@ __device__ __forceinline__ void lds_dma16(const bf16x8 *src, bf16x8 *lds_dst) {
   __builtin_amdgcn_global_load_lds(src, (lds_void *)lds_dst, 16, 0, 0);
 }
 
-template <int KC, int DT>
-__device__ __forceinline__ void lr_block_pair(const bf16x8 *L, const float *Y, int lane, int q,
-                                              const bf16x8 (&thi)[2][KC], const bf16x8 (&tlo)[2][KC],
-                                              f32x4 (&gacc)[2][2 * KC], float (&lq)[2]) {
-  f32x4 z[2][2];
+// forward products of one 32-row block for both chain tiles: z[g][h] holds
+// rows 16 h + 4 q + i (i = 0..3) of chain cl of tile g
+template <int KC>
+__device__ __forceinline__ void lr_fwd(const bf16x8 *L, int lane, const bf16x8 (&thi)[2][KC],
+                                       const bf16x8 (&tlo)[2][KC], f32x4 (&z)[2][2]) {
 #pragma unroll
   for (int g = 0; g < 2; ++g)
 #pragma unroll
@@ -158,10 +165,14 @@ __device__ __forceinline__ void lr_block_pair(const bf16x8 *L, const float *Y, i
         z[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h], tlo[g][kc], z[g][h], 0, 0, 0);
       }
   }
-  const float4 y0 = *reinterpret_cast<const float4 *>(Y + 4 * q);
-  const float4 y1 = *reinterpret_cast<const float4 *>(Y + 16 + 4 * q);
-  const float yv[2][4] = {{y0.x, y0.y, y0.z, y0.w}, {y1.x, y1.y, y1.z, y1.w}};
-  bf16x8 rb[2];
+}
+
+// epilogue of one block: residuals r (bf16, the backward B operand) and the
+// per-chain log-density part; a block past the split's end (use = false)
+// contributes nothing
+__device__ __forceinline__ void lr_epi(const f32x4 (&z)[2][2], const float4 (&yl)[2], bool use, bf16x8 (&rb)[2],
+                                       float (&lq)[2]) {
+  const float yv[2][4] = {{yl[0].x, yl[0].y, yl[0].z, yl[0].w}, {yl[1].x, yl[1].y, yl[1].z, yl[1].w}};
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     float ab = 0.f, prod = 1.f;
@@ -173,39 +184,42 @@ __device__ __forceinline__ void lr_block_pair(const bf16x8 *L, const float *Y, i
         const float e = __builtin_amdgcn_exp2f(-fabsf(zz));
         const float ope = 1.0f + e;
         const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
-        rb[g][4 * h + i] = (__bf16)(yv[h][i] - copysignf(t, zz));
+        rb[g][4 * h + i] = (__bf16)(use ? yv[h][i] - copysignf(t, zz) : 0.f);
         ab += fabsf(zz);
         prod *= ope;
       }
     // prod lies in [1, 256]: the hardware log2 is accurate there
-    lq[g] += fmaf(0.5f, ab, __builtin_amdgcn_logf(prod));
+    lq[g] = use ? fmaf(0.5f, ab, __builtin_amdgcn_logf(prod)) : 0.f;
   }
-  // the DT output tiles of 16 dims that hold dims < d (a tile wholly past d,
-  // e.g. the eighth for d = 100, is all padding and skipped)
-  bf16x8 bfr[DT];
+}
+
+// backward products: the DT output tiles of 16 dims that hold dims < d (a
+// tile wholly past d, e.g. the eighth for d = 100, is all padding)
+template <int KC, int DT>
+__device__ __forceinline__ void lr_bwd(const bf16x8 *L, int lane, const bf16x8 (&rb)[2], f32x4 (&gacc)[2][2 * KC]) {
 #pragma unroll
-  for (int dc = 0; dc < DT; ++dc) bfr[dc] = L[2 * KC * 64 + dc * 64 + lane];
+  for (int dc = 0; dc < DT; ++dc) {
+    const bf16x8 bfr = L[2 * KC * 64 + dc * 64 + lane];
 #pragma unroll
-  for (int dc = 0; dc < DT; ++dc)
-#pragma unroll
-    for (int g = 0; g < 2; ++g) gacc[g][dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[dc], rb[g], gacc[g][dc], 0, 0, 0);
+    for (int g = 0; g < 2; ++g) gacc[g][dc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr, rb[g], gacc[g][dc], 0, 0, 0);
+  }
 }
 
 template <int KC, int DT>
-__global__ void __launch_bounds__(256, 2) k_lr_grad_bf16_pair(LogregArgs a) {
+__global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pipe(LogregArgs a) {
   if (!lr_gate(a)) return;
-  constexpr int kThr = 256;
+  constexpr int kThr = 512;
   constexpr int kFrag = 4 * KC * 64;      // 16-byte fragments per 32-row block
-  constexpr int kPer = 2 * kFrag / kThr;   // fragments per thread per iteration
+  constexpr int kPer = 2 * kFrag / kThr;   // fragments per thread per stage
   constexpr int kBuf = 2 * kFrag + 16;     // one buffer: two blocks' fragments + their 2 x 32 labels
   constexpr int kBlk = 2 * KC * 64;        // forward (or backward) fragments of one block
-  extern __shared__ bf16x8 lds[];          // [2 buffers][kBuf]
+  __shared__ bf16x8 B0[kBuf], B1[kBuf], B2[kBuf];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int pg = wave & 1, rh = wave >> 1;
+  const int pg = wave & 3, rh = wave >> 2;
   const int q = lane >> 4, cl = lane & 15;
   const int64_t N = a.N, ld = a.ld, n = a.n;
-  const int64_t mbase = (int64_t)blockIdx.x * 64 + pg * 32 + cl;  // chain of tile g: mbase + 16 g
+  const int64_t mbase = (int64_t)blockIdx.x * 128 + pg * 32 + cl;  // chain of tile g: mbase + 16 g
   const float *X = static_cast<const float *>(a.x);
   const LrOffsets off = logreg_layout(1, n, a.d, N, ld, a.S);
   const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
@@ -215,13 +229,40 @@ __global__ void __launch_bounds__(256, 2) k_lr_grad_bf16_pair(LogregArgs a) {
   const int b0 = s * a.bps;
   const int b1 = (b0 + a.bps < a.NB) ? b0 + a.bps : a.NB;
   const int nit = (b1 - b0 + 1) / 2;
-  // Iteration it stages blocks b0 + 2 it (half 0) and b0 + 2 it + 1 (half 1).
+  // theta log2(e) of both chain tiles, split into bf16 hi + lo (B operand:
+  // k slot 8q + j of chunk kc is coordinate 32 kc + 16 (j / 4) + 4 q + j % 4);
+  // loaded before the first stage is issued
+  // (every load is issued, from a clamped in-bounds address, and masked
+  // afterwards, so that the sixteen loads are in flight together)
+  float4 tv[2][KC][2];
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int64_t m = mbase + 16 * g;
+    const int64_t mc = m < N ? m : N - 1;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
+        tv[g][kc][hh] = *reinterpret_cast<const float4 *>(X + mc * ld + (d4 < ld ? d4 : 0));
+      }
+  }
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const bool mv = mbase + 16 * g < N;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh)
+        if (!(mv && 32 * kc + 16 * hh + 4 * q < ld)) tv[g][kc][hh] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  // Stage it holds blocks b0 + 2 it (half 0) and b0 + 2 it + 1 (half 1).
   // Fragment c of a buffer belongs to half c / kFrag; inside a block the
   // forward fragments precede the backward ones.  A wavefront's 64 fragments
   // of one instruction lie in one block, so the block test is uniform per
   // wavefront; lanes 0..15 of wavefront 0 also stage the labels.  A
-  // fragment's source is a uniform base (advanced by two blocks per
-  // iteration) plus a loop-invariant per-thread offset.
+  // fragment's source is a uniform base (advanced by two blocks per stage)
+  // plus a loop-invariant per-thread offset.
   const bf16x8 *baseF = XF + (int64_t)b0 * kBlk, *baseB = XB + (int64_t)b0 * kBlk;
   int offk[kPer], halfk[kPer];
   bool fwdk[kPer], usek[kPer];
@@ -235,32 +276,29 @@ __global__ void __launch_bounds__(256, 2) k_lr_grad_bf16_pair(LogregArgs a) {
     // backward fragments of an all-padding output tile are never read
     usek[k] = f < kBlk || (f - kBlk) / 64 < DT;
   }
-  auto stage = [&](int it, int buf) {
+  auto stage = [&](int it, bf16x8 *buf) {
+    if (it >= nit) return;
     const int64_t step = (int64_t)it * 2 * kBlk;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       if (usek[k] && b0 + 2 * it + halfk[k] < b1)
-        lds_dma16((fwdk[k] ? baseF : baseB) + step + offk[k], lds + buf * kBuf + kThr * k + 64 * wave);
+        lds_dma16((fwdk[k] ? baseF : baseB) + step + offk[k], buf + kThr * k + 64 * wave);
     }
     if (tid < 16) {
       const int64_t blk = b0 + 2 * it + (tid >> 3);
-      if (blk < b1) lds_dma16(YF + blk * 8 + (tid & 7), lds + buf * kBuf + 2 * kFrag);
+      if (blk < b1) lds_dma16(YF + blk * 8 + (tid & 7), buf + 2 * kFrag);
     }
   };
-  stage(0, 0);
-  // theta log2(e) of both chain tiles, split into bf16 hi + lo (B operand:
-  // k slot 8q + j of chunk kc is coordinate 32 kc + 16 (j / 4) + 4 q + j % 4)
+  stage(0, B0);
+  stage(1, B1);
   bf16x8 thi[2][KC], tlo[2][KC];
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    const int64_t m = mbase + 16 * g;
+  for (int g = 0; g < 2; ++g)
 #pragma unroll
-    for (int kc = 0; kc < KC; ++kc) {
+    for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
-        const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (m < N && d4 < ld) v = *reinterpret_cast<const float4 *>(X + m * ld + d4);
+        const float4 v = tv[g][kc][hh];
         const float f[4] = {v.x * 1.4426950408889634f, v.y * 1.4426950408889634f, v.z * 1.4426950408889634f,
                             v.w * 1.4426950408889634f};
 #pragma unroll
@@ -270,53 +308,68 @@ __global__ void __launch_bounds__(256, 2) k_lr_grad_bf16_pair(LogregArgs a) {
           tlo[g][kc][4 * hh + i] = (__bf16)(f[i] - (float)hi);
         }
       }
-    }
-  }
   f32x4 gacc[2][2 * KC];
 #pragma unroll
   for (int g = 0; g < 2; ++g)
 #pragma unroll
     for (int dc = 0; dc < 2 * KC; ++dc) gacc[g][dc] = f32x4{0.f, 0.f, 0.f, 0.f};
   double lacc[2] = {0.0, 0.0};
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  for (int it = 0; it < nit; ++it) {
-    // the other buffer was last read in iteration it - 1, which ended in a barrier
-    if (it + 1 < nit) stage(it + 1, (it + 1) & 1);
-    const int64_t blk = b0 + 2 * it + rh;
-    if (blk < b1) {
-      const bf16x8 *L = lds + (it & 1) * kBuf + rh * kFrag;
-      const float *Y = reinterpret_cast<const float *>(lds + (it & 1) * kBuf + 2 * kFrag + 8 * rh);
-      float lq[2] = {0.f, 0.f};
-      lr_block_pair<KC, DT>(L, Y, lane, q, thi, tlo, gacc, lq);
-      // rows of this lane past n: each contributed a factor 2 (log2 = 1)
-      const int64_t nv = n - 32 * blk;
-      if (nv < 32) {
-        int pad = 0;
+  // rows of the wavefront's last block past n: each contributed a factor 2 (log2 = 1)
+  float padc = 0.f;
+  {
+    const int64_t blast = b0 + 2 * (nit - 1) + rh;
+    const int64_t nv = n - 32 * blast;
+    if (nit > 0 && blast < b1 && nv < 32)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) pad += (16 * h + 4 * q + i >= nv) ? 1 : 0;
-        lq[0] -= (float)pad;
-        lq[1] -= (float)pad;
-      }
-      lacc[0] += (double)lq[0];
-      lacc[1] += (double)lq[1];
-    }
-    // this thread's fragments of iteration it + 1 are in LDS; the barrier
-    // publishes everyone's and retires the reads of the current buffer
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+        for (int i = 0; i < 4; ++i) padc += (16 * h + 4 * q + i >= nv) ? 1.f : 0.f;
   }
+  __syncthreads();  // stages 0 and 1 complete and visible
+  f32x4 zc[2][2];
+  lr_fwd<KC>(B0 + rh * kFrag, lane, thi, tlo, zc);
+  // one iteration: stage it + 2 into Bn, forward of the next block from Bf,
+  // epilogue and backward of the current block from Bc
+  auto iter = [&](int it, const bf16x8 *Bc, const bf16x8 *Bf, bf16x8 *Bn) {
+    // the current block's labels are read before the next stage's DMA is issued
+    const float *Y = reinterpret_cast<const float *>(Bc + 2 * kFrag + 8 * rh);
+    const float4 yl[2] = {*reinterpret_cast<const float4 *>(Y + 4 * q), *reinterpret_cast<const float4 *>(Y + 16 + 4 * q)};
+    stage(it + 2, Bn);
+    const bool use = b0 + 2 * it + rh < b1;
+    f32x4 zn[2][2];
+    lr_fwd<KC>(Bf + rh * kFrag, lane, thi, tlo, zn);
+    bf16x8 rb[2];
+    float lq[2];
+    lr_epi(zc, yl, use, rb, lq);
+    // a block past the split's end (stale LDS, possibly not finite) is never multiplied in
+    if (use) lr_bwd<KC, DT>(Bc + rh * kFrag, lane, rb, gacc);
+    lacc[0] += (double)lq[0];
+    lacc[1] += (double)lq[1];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) zc[g][h] = zn[g][h];
+    // stage it + 2 complete and visible; every wavefront is done with Bc
+    __syncthreads();
+  };
+  for (int it = 0; it < nit; it += 3) {
+    iter(it, B0, B1, B2);
+    if (it + 1 < nit) iter(it + 1, B1, B2, B0);
+    if (it + 2 < nit) iter(it + 2, B2, B0, B1);
+  }
+  lacc[0] -= (double)padc;
+  lacc[1] -= (double)padc;
   // half 1 hands its partial sums to half 0 through LDS (fixed order: half 0 + half 1);
   // a lane's four values of a tile are consecutive dims, moved as one 16-byte word
-  f32x4 *red = reinterpret_cast<f32x4 *>(lds);
-  double *lred = reinterpret_cast<double *>(red + 2 * 2 * 2 * KC * 64);
+  // (tile g = 0 through B0, g = 1 through B1, the log-density sums through B2)
+  f32x4 *const red[2] = {reinterpret_cast<f32x4 *>(B0), reinterpret_cast<f32x4 *>(B1)};
+  double *lred = reinterpret_cast<double *>(B2);
+  static_assert(kBuf >= 4 * 2 * KC * 64 && kBuf * 2 >= 4 * 2 * 64, "reduction buffers");
   if (rh == 1) {
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
 #pragma unroll
-      for (int dc = 0; dc < 2 * KC; ++dc) red[((pg * 2 + g) * 2 * KC + dc) * 64 + lane] = gacc[g][dc];
+      for (int dc = 0; dc < 2 * KC; ++dc) red[g][(pg * 2 * KC + dc) * 64 + lane] = gacc[g][dc];
       lred[(pg * 2 + g) * 64 + lane] = lacc[g];
     }
   }
@@ -331,7 +384,7 @@ __global__ void __launch_bounds__(256, 2) k_lr_grad_bf16_pair(LogregArgs a) {
         for (int dc = 0; dc < 2 * KC; ++dc) {
           const int64_t dd = 16 * dc + 4 * q;  // ld is a multiple of 8, so dd < ld covers dd .. dd + 3
           if (dd < ld) {
-            const f32x4 v = gacc[g][dc] + red[((pg * 2 + g) * 2 * KC + dc) * 64 + lane];
+            const f32x4 v = gacc[g][dc] + red[g][(pg * 2 * KC + dc) * 64 + lane];
             *reinterpret_cast<f32x4 *>(Gp + dd) = v;
           }
         }
@@ -851,24 +904,17 @@ hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
     return hipGetLastError();
   }
   if (a.KC < 1 || a.KC > 4) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((a.N + 63) / 64), (unsigned)a.S);
-  // staging: two buffers of two blocks' fragments and labels; the final
-  // hand-over of half 1's partial sums reuses the same memory
-  const size_t stage = (size_t)2 * (2 * 4 * a.KC * 64 + 16) * 16;
-  const size_t red = (size_t)2 * 2 * 2 * a.KC * 64 * 16 + (size_t)2 * 2 * 64 * 8;
-  const size_t shm = stage > red ? stage : red;
+  const dim3 grid((unsigned)((a.N + 127) / 128), (unsigned)a.S);
   // output tiles of 16 dims holding dims < d: 2 KC - 1 or 2 KC
   const bool odd = (a.d + 15) / 16 < 2 * a.KC;
-  void (*const fns[4][2])(LogregArgs) = {{k_lr_grad_bf16_pair<1, 2>, k_lr_grad_bf16_pair<1, 1>},
-                                         {k_lr_grad_bf16_pair<2, 4>, k_lr_grad_bf16_pair<2, 3>},
-                                         {k_lr_grad_bf16_pair<3, 6>, k_lr_grad_bf16_pair<3, 5>},
-                                         {k_lr_grad_bf16_pair<4, 8>, k_lr_grad_bf16_pair<4, 7>}};
+  void (*const fns[4][2])(LogregArgs) = {{k_lr_grad_bf16_pipe<1, 2>, k_lr_grad_bf16_pipe<1, 1>},
+                                         {k_lr_grad_bf16_pipe<2, 4>, k_lr_grad_bf16_pipe<2, 3>},
+                                         {k_lr_grad_bf16_pipe<3, 6>, k_lr_grad_bf16_pipe<3, 5>},
+                                         {k_lr_grad_bf16_pipe<4, 8>, k_lr_grad_bf16_pipe<4, 7>}};
   void (*fn)(LogregArgs) = fns[a.KC - 1][odd ? 1 : 0];
-  const hipError_t e = grant_lds(reinterpret_cast<const void *>(fn), shm);
-  if (e != hipSuccess) return e;
   LogregArgs arg = a;
   void *args[] = {&arg};
-  return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, dim3(256), args, shm, s);
+  return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, dim3(512), args, 0, s);
 }
 
 hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, int block, size_t shmem, hipStream_t s) {
