@@ -191,9 +191,11 @@ def time_to_bias(prec, threshold=0.01, target="gauss", n_adj=N_ADJ):
     e_t = torch.as_tensor(e_ref, device="cuda:0", dtype=torch.float64)
     v_t = torch.as_tensor(v_ref, device="cuda:0", dtype=torch.float64)
 
-    def b2():
+    def b2(argmax=False):
         x = s.positions().to(torch.float64)
         b = ((x * x).mean(0) - e_t) ** 2 / v_t
+        if argmax:
+            return float(b.max()), float(b.mean()), int(b.argmax())
         return float(b.max()), float(b.mean())
 
     n_u = n_a = 0
@@ -217,9 +219,9 @@ def time_to_bias(prec, threshold=0.01, target="gauss", n_adj=N_ADJ):
             st = s.stats()
             hit = dict(n_unadj=n_u, n_adj=n_a, t=st["t"], grads_per_chain=st["grads_per_chain"], b2_max=bmax,
                        b2_avg=bavg, phase_at_crossing=st["phase"])
-    final = b2()
+    final = b2(argmax=True)
     out = dict(precision=prec, reached=hit is not None, b2_max_final=final[0], b2_avg_final=final[1],
-               unadjusted_steps_run=n_u)
+               b2_argmax_final=final[2], unadjusted_steps_run=n_u)
     if hit is None:
         return out
     out.update(hit)

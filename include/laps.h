@@ -84,9 +84,9 @@ typedef enum { LAPS_F64 = 0, LAPS_F32 = 1, LAPS_MIXED_BF16 = 2 } laps_precision;
  *                    row-major, symmetric positive definite); LAPS_F64 or
  *                    LAPS_F32 state.
  * LAPS_LOGREG, LAPS_CALLBACK and LAPS_GAUSS_DENSE run through the per-chain
- * update kernels and are limited to d <= 128 with the second-order (MN2)
- * adjusted integrator: their wider update teams and the MN4 transition are
- * switched off (LAPS_EUNSUPPORTED) after GPU faults whose cause is not found.
+ * update kernels and are limited to d <= 128 (either adjusted integrator):
+ * their wider update teams are switched off (LAPS_EUNSUPPORTED) after GPU
+ * faults whose cause is not found.
  * Target data must stay valid and unchanged while a context uses it. */
 typedef enum {
   LAPS_GAUSS_DIAG = 0,

@@ -296,15 +296,12 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
       if (tg->kind != LAPS_LOGREG && cfg->prec == LAPS_MIXED_BF16)
         return why = "callback and dense Gaussian targets run in LAPS_F64 or LAPS_F32", LAPS_EUNSUPPORTED;
       // These targets share the per-chain update kernels.  Two GPU runs that used their 32- and 64-lane
-      // teams (d > 128) outside the initialisation, with the staged fourth-order transition, faulted the
-      // GPU with no cause shown; both the wide teams and the MN4 transition are refused until one is.
+      // teams (d > 128) outside the initialisation faulted the GPU with no cause shown, so those teams are
+      // refused until one is.  With teams of at most 16 lanes the staged MN4 transition runs the same
+      // device code as MN2 (only the stage count and the host-supplied coefficients differ).
       if (cfg->d > kUpdateMaxD)
         return why = "logistic-regression, callback and dense Gaussian targets support d <= 128 (their 32- and "
                      "64-lane update teams are switched off)",
-               LAPS_EUNSUPPORTED;
-      if (integ_for(cfg) == 2)
-        return why = "logistic-regression, callback and dense Gaussian targets with the MN4 integrator "
-                     "(integrator_adj = 2) are switched off",
                LAPS_EUNSUPPORTED;
       break;
     default:
@@ -380,6 +377,7 @@ LogregArgs logreg_args(laps_ctx *c, int gate) {
     logreg_splits(a.n, a.N, c->cfg.prec, a.d, c->cfg.grad_workgroups, a.S, a.NB, a.bps);
     a.prior = 1;
     a.wy_term = c->cfg.prec == LAPS_F64 ? 0 : 1;
+    a.theta_pack = c->cfg.prec == LAPS_F64 ? 0 : 1;
   }
   a.KC = (int)((a.d + 31) / 32);
   a.T = c->T;
@@ -519,6 +517,7 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     if (dense && !c->packed_ok) e = launch_dense_pack(prec == LAPS_F64 ? 0 : 1, a, c->stream);
     if (!cb && !dense && prec != LAPS_F64 && !c->packed_ok) e = launch_logreg_pack(a, c->stream);
     if (e == hipSuccess) c->packed_ok = true;
+    if (e == hipSuccess && a.theta_pack) e = launch_logreg_theta(a, c->stream);
     if (e == hipSuccess) e = grad(a);
     if (e == hipSuccess) e = upd(a, LR_INIT, 0, 0);
   } else if (kk == KK_UNADJ) {
@@ -870,7 +869,10 @@ extern "C" laps_status laps_eval(laps_ctx *c, const void *x_dev, void *logp_dev,
       return LAPS_EDEVICE;
     }
   } else {
-    e = launch_logreg_grad(prec, a, c->stream);
+    // the packed theta of the caller's positions; the next gradient of the run is preceded by an update
+    // kernel that packs the run's own positions again
+    if (a.theta_pack) e = launch_logreg_theta(a, c->stream);
+    if (e == hipSuccess) e = launch_logreg_grad(prec, a, c->stream);
   }
   if (e == hipSuccess) {
     a.mode = LR_EVAL;

@@ -61,12 +61,18 @@ def test_initial_gradient_and_logp(gpu, orc, prec, N, d):
     assert np.all(np.abs(lp - lref) <= ltol * lscale)
 
 
+@pytest.mark.parametrize("integ", [1, 2])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("N,d", [(70, 37), (64, 100)])
-def test_steps_and_transitions(gpu, orc, prec, N, d):
+def test_steps_and_transitions(gpu, orc, prec, N, d, integ):
+    """Unadjusted steps and MAMS transitions with MN2 (integ 1) and MN4
+    (integ 2) against the oracle.  FP32 positions after the transitions are
+    held to 2.5 x the MN2 tolerance under MN4, which takes five gradient
+    stages per step instead of two, each adding its FP32 rounding of the
+    dense product (measured 1.8e-4 at d = 100)."""
     import torch
     w = workloads.ill_gaussian(n_chains=N, d=d)
-    cfg = dict(switch_policy=1, max_steps_unadj=15, max_steps_total=15 + 15 * 3, integrator_adj=1)
+    cfg = dict(switch_policy=1, max_steps_unadj=15, max_steps_total=15 + 15 * 3, integrator_adj=integ)
     s = gpu.Sampler(w, prec, **cfg)
     o = orc.Ensemble(orc.Target.from_workload(w), N, w["seed"], **cfg)
     o.init(w["x0"])
@@ -96,4 +102,4 @@ def test_steps_and_transitions(gpu, orc, prec, N, d):
         assert not flipped.any()
     assert flipped.mean() <= 0.05
     err = _rel_rows(s.positions().cpu().numpy(), o.array("x"))
-    assert np.max(err[~flipped]) < TOL[prec]
+    assert np.max(err[~flipped]) < TOL[prec] * (2.5 if integ == 2 and prec == "f32" else 1.0)

@@ -126,6 +126,7 @@ def test_logistic_full_size_sampled_gradients(gpu, orc):
     X, y = w["X"], w["y"]
     ot = orc.Target.from_workload(w)
     rows = np.random.default_rng(77).choice(w["n_chains"], size=48, replace=False)
+    worst_l = worst_lb = worst_g = worst_gr = 0.0
     for m in rows:
         th = th_all[m]
         l_ref, g_ref = ot.logp_grad(th)
@@ -140,6 +141,12 @@ def test_logistic_full_size_sampled_gradients(gpu, orc):
         dr = 2.0**-9 * np.abs(y - sig) + 0.25 * dz + 1e-7
         bound_g = np.abs(X).T @ dr + 1e-5 * (np.abs(X).T @ np.abs(y - sig)) + 1e-6 * np.abs(th)
         assert np.all(np.abs(g_all[m] - g_ref) <= bound_g), (m, np.max(np.abs(g_all[m] - g_ref) / bound_g))
+        worst_l = max(worst_l, abs(lp_all[m] - l_ref))
+        worst_lb = max(worst_lb, bound_l)
+        worst_g = max(worst_g, float(np.max(np.abs(g_all[m] - g_ref))))
+        worst_gr = max(worst_gr, float(np.linalg.norm(g_all[m] - g_ref) / np.linalg.norm(g_ref)))
+    print(f"bf16 gradient at C2 size vs FP64 oracle (48 chains): max |d log p| {worst_l:.2e} "
+          f"(largest bound {worst_lb:.2e}), max |d g_i| {worst_g:.2e}, max |dg|/|g| {worst_gr:.2e}")
 
 
 def test_logistic_full_run_moments_against_reference(gpu):

@@ -236,15 +236,25 @@ def test_mixed_transitions_against_oracle_on_identical_states(gpu, orc, shape):
           f"max rel x err {worst_x:.2e}, decision flips {flips_total}/{N * n_adj}")
 
 
-@pytest.mark.skip(reason="the logistic-regression MN4 transition (d = 204, 32-lane update teams) faulted the GPU "
-                         "(illegal memory access) with no cause shown yet; the library refuses that configuration")
 @pytest.mark.parametrize("prec", ["f64", "bf16"])
-def test_fourth_order_transitions(gpu, orc, prec):
-    """d > 200 selects the MN4 integrator for the adjusted phase: five
-    gradient stages per step through the per-chain update kernel.  FP64
-    against the oracle at 1e-10; bf16 with the oracle replaying eps."""
-    w = _w(40, 150, 204, seed=5)
-    cfg = dict(switch_policy=1, max_steps_unadj=8, max_steps_total=8 + 15 * 3)
+@pytest.mark.parametrize("shape", [
+    (40, 150, 100), (70, 300, 37),
+    pytest.param((40, 150, 204), marks=pytest.mark.skip(
+        reason="the logistic-regression MN4 transition at d = 204 (32-lane update teams) faulted the GPU "
+               "(illegal memory access) with no cause shown yet; the library refuses d > 128"))])
+def test_fourth_order_transitions(gpu, orc, prec, shape):
+    """The MN4 integrator in the adjusted phase (the automatic choice above
+    d = 200, asked for explicitly here): five gradient stages per step
+    through the per-chain update kernel.  FP64 runs free (both controllers
+    their own) with eps within 1e-9 and positions within 3e-10: the two
+    transitions take 150 gradient stages per chain, each summed in another
+    order by the matrix-core kernel than by the oracle (~1e-15 relative), and
+    the step sizes of the free controllers differ in the last digits (the
+    MN2 tests, with two stages per step instead of five, hold 1e-10).  bf16
+    with the oracle replaying eps."""
+    N, n, d = shape
+    w = _w(N, n, d, seed=5)
+    cfg = dict(switch_policy=1, max_steps_unadj=8, max_steps_total=8 + 15 * 3, integrator_adj=2)
     o = _oracle(orc, w, **cfg)
     s = gpu.Sampler(w, prec, **cfg)
     replay = prec != "f64"
@@ -262,10 +272,12 @@ def test_fourth_order_transitions(gpu, orc, prec):
         so, sg = o.stats(), s.stats()
         assert so["integrator"] == sg["integrator"] == 2 and so["t"] == sg["t"]
         assert sg["n_nonfinite"] == 0
+        if not replay:
+            assert abs(sg["eps"] - so["eps"]) <= 1e-9 * so["eps"], (k, sg["eps"], so["eps"])
     x, xo = s.positions().cpu().numpy(), o.array("x")
     err = _rel_rows(x, xo)
     if prec == "f64":
-        assert np.max(err) < 1e-10, np.max(err)
+        assert np.max(err) < 3e-10, np.max(err)
         np.testing.assert_allclose(s.buffer("acc").cpu().numpy(), o.array("acc"), rtol=0, atol=1e-8)
     else:
         # chains whose accept decision flips between the two (U within the bf16 energy error) are excluded
