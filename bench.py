@@ -53,6 +53,29 @@ PEAK_HBM_GBS = 8000.0
 # and WRITE_SIZE counters scaled by what they read for a plain copy of known size; kept with the counter
 # summary under profiles/ and reset to None whenever the kernel changes.
 LR_GRAD_TRAFFIC_BYTES = 35.09e6
+# Instructions per launch of the same kernel (SQ_INSTS_VALU, which includes the MFMA instructions,
+# SQ_INSTS_MFMA and SQ_INSTS_VALU_TRANS_F32, mean per dispatch), kept with the counter summary under
+# profiles/ and reset to None whenever the kernel changes: they give the vector-ALU ceiling reported
+# next to the matrix-core one.
+LR_GRAD_INSTS = {"valu": 5825889, "mfma": 994048, "trans": 685568}
+SIMDS, CLOCK_HZ = 1024, 2.4e9  # 256 CUs x 4 SIMDs at 2.4 GHz
+# Vector instructions (SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32) per launch of the per-chain step kernels,
+# from the counter summary under profiles/; reset to None whenever a kernel changes.
+STEP_INSTS = {
+    "stochvol": {"unadj": (32497665, 913409), "mams": (942860609, 27885571)},
+    "phi4": {"unadj": (22034432, 577536), "mams": (552040953, 9981952)},
+}
+
+
+def _valu_ceiling(valu, trans, kernel_ms, mfma=0):
+    """Vector-ALU issue time of a launch spread over every SIMD (a wave64 vector instruction occupies a
+    SIMD 4 cycles, a transcendental 16, an MFMA instruction, counted in valu, none of the vector ALU)
+    against the kernel's duration."""
+    cyc = (valu - mfma) * 4 + trans * 12
+    t_valu = cyc / (SIMDS * CLOCK_HZ)
+    t_k = kernel_ms * 1e-3
+    return {"bound": "alu", "achieved": cyc / t_k / 1e9, "peak": SIMDS * CLOCK_HZ / 1e9,
+            "unit": "G SIMD-cycles/s of vector-ALU issue", "frac": t_valu / t_k, "valu_issue_us": t_valu * 1e6}
 N_UNADJ, N_ADJ = 1000, 67
 # the dominant kernel's launches bracketed by HIP events inside the timed runs: one in LOG_EVERY
 LOG_EVERY = int(os.environ.get("LAPS_BENCH_LOG_EVERY", "10"))
@@ -285,6 +308,12 @@ def main():
                 "kernel": "k_lr_grad_bf16_pipe<4, 7>" if prec == "bf16" else "k_lr_grad_f64", "kernel_ms": kern["ms"],
                 "launches_timed": kern["launches"], "isolated_kernel_ms": r["grad_ms"],
                 "algorithmic_flops_per_launch": work}
+        if prec == "bf16" and LR_GRAD_INSTS:
+            vc = _valu_ceiling(LR_GRAD_INSTS["valu"], LR_GRAD_INSTS["trans"], kern["ms"], LR_GRAD_INSTS["mfma"])
+            t_mfma = LR_GRAD_INSTS["mfma"] * 16 / (SIMDS * CLOCK_HZ)  # 16 cycles per 16x16x32 bf16 MFMA
+            vc["mfma_issue_us"] = t_mfma * 1e6
+            vc["frac_of_valu_plus_mfma_in_series"] = (vc["valu_issue_us"] * 1e-6 + t_mfma) / (kern["ms"] * 1e-3)
+            roof["valu_ceiling"] = vc
         precision = ("bf16 matrix-core gradient, fp32 state, fp64 energy error and reductions"
                      if prec == "bf16" else "fp64 throughout")
         extra = {"n": n}
@@ -312,6 +341,10 @@ def main():
                 "kernel_ms": kern["ms"], "launches_timed": kern["launches"], "isolated_kernel_ms": unadj_ms,
                 "algorithmic_bytes_per_launch": work, "kept_gradient_bytes_per_launch": kept_g,
                 "adjusted_transition_kernel_ms": adj_ms, "gradient_only_ms": r["grad_ms"]}
+        insts = STEP_INSTS.get(args.workload) if prec == "f32" else None
+        if insts:
+            roof["valu_ceiling"] = _valu_ceiling(*insts["unadj"], kern["ms"])
+            roof["adjusted_transition_valu_ceiling"] = _valu_ceiling(*insts["mams"], adj_ms)
         precision = "fp64 throughout" if prec == "f64" else "fp32 state, fp64 energy error and reductions"
         extra = {}
     line = {

@@ -377,7 +377,6 @@ LogregArgs logreg_args(laps_ctx *c, int gate) {
     logreg_splits(a.n, a.N, c->cfg.prec, a.d, c->cfg.grad_workgroups, a.S, a.NB, a.bps);
     a.prior = 1;
     a.wy_term = c->cfg.prec == LAPS_F64 ? 0 : 1;
-    a.theta_pack = c->cfg.prec == LAPS_F64 ? 0 : 1;
   }
   a.KC = (int)((a.d + 31) / 32);
   a.T = c->T;
@@ -517,7 +516,6 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     if (dense && !c->packed_ok) e = launch_dense_pack(prec == LAPS_F64 ? 0 : 1, a, c->stream);
     if (!cb && !dense && prec != LAPS_F64 && !c->packed_ok) e = launch_logreg_pack(a, c->stream);
     if (e == hipSuccess) c->packed_ok = true;
-    if (e == hipSuccess && a.theta_pack) e = launch_logreg_theta(a, c->stream);
     if (e == hipSuccess) e = grad(a);
     if (e == hipSuccess) e = upd(a, LR_INIT, 0, 0);
   } else if (kk == KK_UNADJ) {
@@ -869,10 +867,7 @@ extern "C" laps_status laps_eval(laps_ctx *c, const void *x_dev, void *logp_dev,
       return LAPS_EDEVICE;
     }
   } else {
-    // the packed theta of the caller's positions; the next gradient of the run is preceded by an update
-    // kernel that packs the run's own positions again
-    if (a.theta_pack) e = launch_logreg_theta(a, c->stream);
-    if (e == hipSuccess) e = launch_logreg_grad(prec, a, c->stream);
+    e = launch_logreg_grad(prec, a, c->stream);
   }
   if (e == hipSuccess) {
     a.mode = LR_EVAL;

@@ -245,11 +245,13 @@ __global__ void __launch_bounds__(THREADS) k_finalize(CtlArgs c, int mode) {
     Dp = (1.0 - V) * (1.0 - V);
     vp = var;
     if (mode == FIN_UNADJ) c.ring[H->ring_pos * ld + i] = m2;
+    mu_sh[dl] = m2;
   }
   if (full) {
-    __syncthreads();  // the new window entry is visible to the whole block
-    // two-pass mean and sample variance over the window slots
-    // the slots are added in order; eight loads are issued before they are used
+    __syncthreads();  // the new window entry (and the shift) is visible to the whole block
+    // mean and sample variance over the window slots in one pass, about the
+    // newest entry K: mu = K + s1 / Tw, var = (s2 - s1^2 / Tw) / (Tw - 1)
+    const double K = mu_sh[dl];
     double w1[4] = {0.0, 0.0, 0.0, 0.0};
     if (act) {
       int64_t k = rg;
@@ -258,35 +260,24 @@ __global__ void __launch_bounds__(THREADS) k_finalize(CtlArgs c, int mode) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) r[j] = c.ring[(k + j * kFinGroups) * ld + i];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) w1[0] += r[j];
-      }
-      for (; k < c.Tw; k += kFinGroups) w1[0] += c.ring[k * ld + i];
-    }
-    fin_combine<DIMS>(w1, sh, dl, rg);
-    if (rg == 0) mu_sh[dl] = w1[0] / (double)c.Tw;
-    __syncthreads();
-    const double mu = mu_sh[dl];
-    double w2[4] = {0.0, 0.0, 0.0, 0.0};
-    if (act) {
-      int64_t k = rg;
-      for (; k + 7 * kFinGroups < c.Tw; k += 8 * kFinGroups) {
-        double r[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) r[j] = c.ring[(k + j * kFinGroups) * ld + i];
-#pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const double e = r[j] - mu;
-          w2[0] += e * e;
+          const double e = r[j] - K;
+          w1[0] += e;
+          w1[1] += e * e;
         }
       }
       for (; k < c.Tw; k += kFinGroups) {
-        const double e = c.ring[k * ld + i] - mu;
-        w2[0] += e * e;
+        const double e = c.ring[k * ld + i] - K;
+        w1[0] += e;
+        w1[1] += e * e;
       }
     }
-    fin_combine<DIMS>(w2, sh, dl, rg);
+    fin_combine<DIMS>(w1, sh, dl, rg);
     if (rg == 0 && act) {
-      wd = sqrt(w2[0] / (double)(c.Tw - 1)) / mu;
+      const double Tw = (double)c.Tw;
+      const double mu = K + w1[0] / Tw;
+      const double vw = (w1[1] - w1[0] * (w1[0] / Tw)) / (Tw - 1.0);
+      wd = sqrt(vw > 0.0 ? vw : 0.0) / mu;
       c.wdelta[i] = wd;
     }
   }

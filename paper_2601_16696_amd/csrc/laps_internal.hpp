@@ -130,8 +130,6 @@ struct LogregArgs {
   int cK;
   int prior;               // 1: add the N(0, I) prior of logistic regression to the partial sums; 0: caller's log p
   int wy_term;             // 1: add theta . (X^T (y - 1/2)), left out of the bf16 gradient's split sums
-  int theta_pack;          // 1: the update kernels also write theta log2(e) split into bf16 hi + lo, in the
-                           // bf16 gradient's operand layout, wherever they move x ahead of a gradient
   double *logp_out;        // LR_EVAL: log p output [N]
   void *g_out;             // LR_EVAL: gradient output [N][ld] (or null)
 };
@@ -139,7 +137,7 @@ struct LogregArgs {
 enum { LR_INIT = 0, LR_PRE = 1, LR_POST = 2, LR_MBEGIN = 3, LR_MSTEP = 4, LR_EVAL = 5 };
 
 struct LrOffsets {
-  size_t Xf, Xb, yf, wy, tp, Gp, lp, x0, g0, sc, total;
+  size_t Xf, Xb, yf, wy, Gp, lp, x0, g0, sc, total;
 };
 __host__ __device__ inline size_t lr_al256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -157,10 +155,6 @@ __host__ __device__ inline LrOffsets logreg_layout(int prec, int64_t n, int64_t 
   off = lr_al256(off + (bf ? (size_t)NB * 32 * 4 : 0));
   o.wy = off;
   off = lr_al256(off + (bf ? (size_t)ld * 8 : 0));
-  // theta log2(e) as bf16 hi + lo per chain: [KC][hi, lo][4][8] (128 bytes per k chunk), for the chains
-  // of every 128-chain gradient workgroup (those past N stay zero)
-  o.tp = off;
-  off = lr_al256(off + (bf ? (size_t)((N + 127) / 128 * 128) * KC * 128 : 0));
   o.Gp = off;
   off = lr_al256(off + (size_t)S * N * ld * rs);
   o.lp = off;
@@ -178,8 +172,6 @@ __host__ __device__ inline LrOffsets logreg_layout(int prec, int64_t n, int64_t 
 // Row splits of the gradient launch: wgs workgroups aimed for (0: automatic).
 void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int wgs, int &S, int &NB, int &bps);
 hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s);
-// theta of a.x (every chain, zeros past N) into the packed hi + lo operands of the bf16 gradient
-hipError_t launch_logreg_theta(const LogregArgs &a, hipStream_t s);
 hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s);
 hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, int block, size_t shmem, hipStream_t s);
 // Dense-precision Gaussian: the precision matrix copied in the state type

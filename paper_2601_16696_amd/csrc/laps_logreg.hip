@@ -137,51 +137,6 @@ __global__ void k_lr_pack(const unsigned short *X, const double *y, int64_t n, i
 // they give r = 0 and |z| = 0 and a factor of exactly 2 each, whose log2 (1
 // per row) is subtracted.
 // ---------------------------------------------------------------------------
-// theta log2(e) of oct `oct` (coordinates 8 oct .. 8 oct + 7) of one chain,
-// split into bf16 hi + lo and written into the chain's packed B operands tpc
-// ([KC][hi, lo][4][8] bf16).  Coordinate 32 kc + c (c < 32) sits in k slot
-// 8 q + j of chunk kc with c = 16 (j / 4) + 4 q + j % 4, so oct o of a chunk
-// fills slots 4 (o / 2) .. 4 (o / 2) + 3 of q = 2 (o % 2) (its first four
-// coordinates) and of q = 2 (o % 2) + 1 (its last four).
-__device__ __forceinline__ void lr_put_theta(__bf16 *tpc, int oct, const float *v) {
-  const int kc = oct >> 2, o = oct & 3;
-  const int q0 = 2 * (o & 1), j0 = 4 * (o >> 1);
-  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-  bf16x4 w[2][2];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const float f = v[i] * 1.4426950408889634f;
-    const __bf16 hi = (__bf16)f;
-    w[0][i >> 2][i & 3] = hi;
-    w[1][i >> 2][i & 3] = (__bf16)(f - (float)hi);
-  }
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int qq = 0; qq < 2; ++qq)
-      *reinterpret_cast<bf16x4 *>(tpc + kc * 64 + h * 32 + (q0 + qq) * 8 + j0) = w[h][qq];
-}
-
-// packed theta of a.x for every chain of the gradient grid (zeros past N), one
-// thread per (chain, oct)
-__global__ void __launch_bounds__(256) k_lr_theta(LogregArgs a) {
-  const LrOffsets off = logreg_layout(1, a.n, a.d, a.N, a.ld, a.S);
-  const int no = 4 * a.KC;
-  const int64_t Np = (a.N + 127) / 128 * 128;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Np * no) return;
-  const int64_t m = i / no;
-  const int oct = (int)(i - m * no);
-  const float *X = static_cast<const float *>(a.x);
-  float v[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int64_t e = 8 * (int64_t)oct + k;
-    v[k] = (m < a.N && e < a.d) ? X[m * a.ld + e] : 0.f;
-  }
-  lr_put_theta(reinterpret_cast<__bf16 *>(a.scratch + off.tp) + (size_t)m * a.KC * 64, oct, v);
-}
-
 typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ __forceinline__ void lds_dma16(const bf16x8 *src, bf16x8 *lds_dst) {
@@ -265,6 +220,7 @@ __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pipe(LogregArgs a) {
   const int q = lane >> 4, cl = lane & 15;
   const int64_t N = a.N, ld = a.ld, n = a.n;
   const int64_t mbase = (int64_t)blockIdx.x * 128 + pg * 32 + cl;  // chain of tile g: mbase + 16 g
+  const float *X = static_cast<const float *>(a.x);
   const LrOffsets off = logreg_layout(1, n, a.d, N, ld, a.S);
   const bf16x8 *XF = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xf);
   const bf16x8 *XB = reinterpret_cast<const bf16x8 *>(a.scratch + off.Xb);
@@ -273,20 +229,32 @@ __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pipe(LogregArgs a) {
   const int b0 = s * a.bps;
   const int b1 = (b0 + a.bps < a.NB) ? b0 + a.bps : a.NB;
   const int nit = (b1 - b0 + 1) / 2;
-  // theta log2(e) of both chain tiles, split into bf16 hi + lo by the update
-  // kernels (B operand: k slot 8q + j of chunk kc is coordinate
-  // 32 kc + 16 (j / 4) + 4 q + j % 4); every chain of the grid has a packed row
-  // (zeros past N).  Loaded before the first stage is issued.
-  const bf16x8 *TP = reinterpret_cast<const bf16x8 *>(a.scratch + off.tp);
-  bf16x8 thi[2][KC], tlo[2][KC];
+  // theta log2(e) of both chain tiles, split into bf16 hi + lo (B operand:
+  // k slot 8q + j of chunk kc is coordinate 32 kc + 16 (j / 4) + 4 q + j % 4);
+  // loaded before the first stage is issued
+  // (every load is issued, from a clamped in-bounds address, and masked
+  // afterwards, so that the sixteen loads are in flight together)
+  float4 tv[2][KC][2];
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     const int64_t m = mbase + 16 * g;
+    const int64_t mc = m < N ? m : N - 1;
 #pragma unroll
-    for (int kc = 0; kc < KC; ++kc) {
-      thi[g][kc] = TP[(m * KC + kc) * 8 + q];
-      tlo[g][kc] = TP[(m * KC + kc) * 8 + 4 + q];
-    }
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int64_t d4 = 32 * kc + 16 * hh + 4 * q;
+        tv[g][kc][hh] = *reinterpret_cast<const float4 *>(X + mc * ld + (d4 < ld ? d4 : 0));
+      }
+  }
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const bool mv = mbase + 16 * g < N;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh)
+        if (!(mv && 32 * kc + 16 * hh + 4 * q < ld)) tv[g][kc][hh] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   // Stage it holds blocks b0 + 2 it (half 0) and b0 + 2 it + 1 (half 1).
   // Fragment c of a buffer belongs to half c / kFrag; inside a block the
@@ -323,6 +291,23 @@ __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pipe(LogregArgs a) {
   };
   stage(0, B0);
   stage(1, B1);
+  bf16x8 thi[2][KC], tlo[2][KC];
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const float4 v = tv[g][kc][hh];
+        const float f[4] = {v.x * 1.4426950408889634f, v.y * 1.4426950408889634f, v.z * 1.4426950408889634f,
+                            v.w * 1.4426950408889634f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const __bf16 hi = (__bf16)f[i];
+          thi[g][kc][4 * hh + i] = hi;
+          tlo[g][kc][4 * hh + i] = (__bf16)(f[i] - (float)hi);
+        }
+      }
   f32x4 gacc[2][2 * KC];
 #pragma unroll
   for (int g = 0; g < 2; ++g)
@@ -590,19 +575,6 @@ __device__ __forceinline__ double lr_theta_terms(const LogregArgs &a, const LrOf
   return v;
 }
 
-// The lane's oct of the new positions, packed for the next bf16 gradient
-// (lanes past the chain's octs write the zeros of the remaining k chunks).
-template <class Real>
-__device__ __forceinline__ void lr_store_theta(const LogregArgs &a, const LrOffsets &off, int64_t m, int r, int T,
-                                               const Real (&x)[1][8]) {
-  if constexpr (sizeof(Real) == 4) {
-    if (!a.theta_pack) return;
-    __bf16 *tpc = reinterpret_cast<__bf16 *>(a.scratch + off.tp) + (size_t)m * a.KC * 64;
-    const float zero[8] = {};
-    for (int o = r; o < 4 * a.KC; o += T) lr_put_theta(tpc, o, o == r ? x[0] : zero);
-  }
-}
-
 template <class Real>
 __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   if (!lr_gate(a)) return;
@@ -750,7 +722,6 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     if (act) {
       store_row<Real, 1>(X + m * ld, r, T, d, x);
       store_row<Real, 1>(U + m * ld, r, T, d, u);
-      lr_store_theta<Real>(a, off, m, r, T, x);
       if (r == 0) {
         sc_l0[m] = a.logp[m];
         sc_dk[m] = b1.dK;
@@ -810,7 +781,6 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     if (act) {
       store_row<Real, 1>(X + m * ld, r, T, d, x);
       store_row<Real, 1>(U + m * ld, r, T, d, u);
-      lr_store_theta<Real>(a, off, m, r, T, x);
       if (r == 0) {
         sc_l0[m] = l0;
         sc_lprev[m] = l0;
@@ -894,7 +864,6 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     store_row<Real, 1>(X + m * ld, r, T, d, x);
     store_row<Real, 1>(U + m * ld, r, T, d, u);
     store_row<Real, 1>(Gc + m * ld, r, T, d, g);
-    lr_store_theta<Real>(a, off, m, r, T, x);
     if (r == 0) {
       sc_D[m] = D;
       sc_lprev[m] = lprev;
@@ -912,12 +881,6 @@ hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s) {
                      reinterpret_cast<unsigned short *>(a.scratch + off.Xf),
                      reinterpret_cast<unsigned short *>(a.scratch + off.Xb), reinterpret_cast<float *>(a.scratch + off.yf),
                      reinterpret_cast<double *>(a.scratch + off.wy));
-  return hipGetLastError();
-}
-
-hipError_t launch_logreg_theta(const LogregArgs &a, hipStream_t s) {
-  const int64_t total = (a.N + 127) / 128 * 128 * 4 * a.KC;
-  hipLaunchKernelGGL(k_lr_theta, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
