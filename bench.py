@@ -52,12 +52,12 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the bf16 gradient kernel on the logistic-regression workload, from FETCH_SIZE
 # and WRITE_SIZE counters scaled by what they read for a plain copy of known size; kept with the counter
 # summary under profiles/ and reset to None whenever the kernel changes.
-LR_GRAD_TRAFFIC_BYTES = 35.09e6
+LR_GRAD_TRAFFIC_BYTES = 35.08e6
 # Instructions per launch of the same kernel (SQ_INSTS_VALU, which includes the MFMA instructions,
 # SQ_INSTS_MFMA and SQ_INSTS_VALU_TRANS_F32, mean per dispatch), kept with the counter summary under
 # profiles/ and reset to None whenever the kernel changes: they give the vector-ALU ceiling reported
 # next to the matrix-core one.
-LR_GRAD_INSTS = {"valu": 5825889, "mfma": 994048, "trans": 685568}
+LR_GRAD_INSTS = {"valu": 5710817, "mfma": 994048, "trans": 687360}
 SIMDS, CLOCK_HZ = 1024, 2.4e9  # 256 CUs x 4 SIMDs at 2.4 GHz
 # Vector instructions (SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32) per launch of the per-chain step kernels,
 # from the counter summary under profiles/; reset to None whenever a kernel changes.

@@ -167,29 +167,57 @@ __device__ __forceinline__ void lr_fwd(const bf16x8 *L, int lane, const bf16x8 (
   }
 }
 
-// epilogue of one block: residuals r (bf16, the backward B operand) and the
-// per-chain log-density part; a block past the split's end (use = false)
-// contributes nothing
-__device__ __forceinline__ void lr_epi(const f32x4 (&z)[2][2], const float4 (&yl)[2], bool use, bf16x8 (&rb)[2],
-                                       float (&lq)[2]) {
+// Forward products of the next block (into zn) interleaved with the epilogue
+// of the current one (from zc): residuals r (bf16, the backward B operand)
+// and the per-chain log-density part.  The 4 KC MFMA pairs (theta hi, lo) and
+// the 16 (row, chain) epilogue items are spread evenly over each other; an
+// empty asm statement pins each item's results where it is written, so that
+// the compiler keeps the vector-ALU work between the matrix-core instructions
+// instead of sinking it to the end of the block (no instruction is emitted
+// for it).  The two sides are independent, so a wavefront's matrix cores and
+// vector ALU can work at the same time.
+template <int KC>
+__device__ __forceinline__ void lr_fwd_epi(const bf16x8 *L, int lane, const bf16x8 (&thi)[2][KC],
+                                           const bf16x8 (&tlo)[2][KC], const f32x4 (&zc)[2][2], const float4 (&yl)[2],
+                                           f32x4 (&zn)[2][2], bf16x8 (&rb)[2], float (&lq)[2]) {
   const float yv[2][4] = {{yl[0].x, yl[0].y, yl[0].z, yl[0].w}, {yl[1].x, yl[1].y, yl[1].z, yl[1].w}};
+  bf16x8 af[KC][2];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) af[kc][h] = L[(h * KC + kc) * 64 + lane];
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) zn[g][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float ab[2] = {0.f, 0.f}, prod[2] = {1.f, 1.f};
+  float rr[2][8];
+  constexpr int NG = 4 * KC;
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    const int kc = k / 4, h = (k / 2) % 2, g = k % 2;
+    zn[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kc][h], thi[g][kc], zn[g][h], 0, 0, 0);
+    zn[g][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kc][h], tlo[g][kc], zn[g][h], 0, 0, 0);
+    // epilogue items 16 k / NG .. 16 (k + 1) / NG - 1: row 16 eh + 4 q + ei of chain cl of tile eg
+#pragma unroll
+    for (int it = 16 * k / NG; it < 16 * (k + 1) / NG; ++it) {
+      const int eg = it / 8, eh = (it / 4) % 2, ei = it % 4;
+      const float zz = zc[eg][eh][ei];
+      const float e = __builtin_amdgcn_exp2f(-fabsf(zz));
+      const float ope = 1.0f + e;
+      const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
+      rr[eg][4 * eh + ei] = yv[eh][ei] - copysignf(t, zz);
+      ab[eg] += fabsf(zz);
+      prod[eg] *= ope;
+      asm volatile("" : "+v"(rr[eg][4 * eh + ei]), "+v"(ab[eg]), "+v"(prod[eg]));
+    }
+  }
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
-    float ab = 0.f, prod = 1.f;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float zz = z[g][h][i];
-        const float e = __builtin_amdgcn_exp2f(-fabsf(zz));
-        const float ope = 1.0f + e;
-        const float t = __builtin_amdgcn_rcpf(ope) - 0.5f;
-        rb[g][4 * h + i] = (__bf16)(use ? yv[h][i] - copysignf(t, zz) : 0.f);
-        ab += fabsf(zz);
-        prod *= ope;
-      }
+    for (int j = 0; j < 8; ++j) rb[g][j] = (__bf16)rr[g][j];
     // prod lies in [1, 256]: the hardware log2 is accurate there
-    lq[g] = use ? fmaf(0.5f, ab, __builtin_amdgcn_logf(prod)) : 0.f;
+    lq[g] = fmaf(0.5f, ab[g], __builtin_amdgcn_logf(prod[g]));
   }
 }
 
@@ -337,14 +365,16 @@ __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pipe(LogregArgs a) {
     stage(it + 2, Bn);
     const bool use = b0 + 2 * it + rh < b1;
     f32x4 zn[2][2];
-    lr_fwd<KC>(Bf + rh * kFrag, lane, thi, tlo, zn);
     bf16x8 rb[2];
     float lq[2];
-    lr_epi(zc, yl, use, rb, lq);
-    // a block past the split's end (stale LDS, possibly not finite) is never multiplied in
-    if (use) lr_bwd<KC, DT>(Bc + rh * kFrag, lane, rb, gacc);
-    lacc[0] += (double)lq[0];
-    lacc[1] += (double)lq[1];
+    lr_fwd_epi<KC>(Bf + rh * kFrag, lane, thi, tlo, zc, yl, zn, rb, lq);
+    // a block past the split's end (stale LDS, possibly not finite) contributes nothing (a
+    // wavefront-uniform branch)
+    if (use) {
+      lr_bwd<KC, DT>(Bc + rh * kFrag, lane, rb, gacc);
+      lacc[0] += (double)lq[0];
+      lacc[1] += (double)lq[1];
+    }
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
