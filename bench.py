@@ -102,13 +102,13 @@ def _cfg(n_unadj=N_UNADJ, n_adj=N_ADJ):
     return dict(switch_policy=1, max_steps_unadj=n_unadj, max_steps_total=n_unadj + 15 * n_adj)
 
 
-def gpu_throughput(w, prec, steps, warmup, n_unadj=N_UNADJ, n_adj=N_ADJ, log=None):
+def gpu_throughput(w, prec, steps, warmup, n_unadj=N_UNADJ, n_adj=N_ADJ, log=None, **extra):
     """Timed full runs.  log names a kernel ("grad" or "unadj") whose every
     launch inside the timed runs is bracketed by HIP events on the sampler's
     stream; its mean duration is returned as kernel_ms."""
     import torch
     from paper_2601_16696_amd import laps
-    s = laps.Sampler(w, prec, **_cfg(n_unadj, n_adj))
+    s = laps.Sampler(w, prec, **_cfg(n_unadj, n_adj), **extra)
     x0 = torch.as_tensor(w["x0"], device="cuda:0").to(s.x.dtype)
     for _ in range(warmup):
         _run_once(s, x0, n_unadj, n_adj)
@@ -147,6 +147,74 @@ def step_kernel_times(w, prec, n_reps=20):
     adj = s.time_kernel("adj", max(2, n_reps // 4))
     torch.cuda.synchronize()
     return unadj, adj
+
+
+def measured_peaks():
+    """Achievable peaks on this GPU, measured with library code: a streaming copy of 2 GiB (larger than
+    the 256 MB last-level cache), read + write bytes over time, and a bf16 GEMM of 8192^3 through
+    torch.matmul (hipBLASLt), 2 M N K flops over time; the best of 20 timed launches each."""
+    import torch
+    def best(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return min(ts)
+    n = 1 << 29  # floats: 2 GiB per buffer
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    t_copy = best(lambda: b.copy_(a))
+    del a, b
+    m = 8192
+    x = torch.randn(m, m, dtype=torch.bfloat16, device="cuda:0")
+    y = torch.randn(m, m, dtype=torch.bfloat16, device="cuda:0")
+    t_gemm = best(lambda: torch.matmul(x, y))
+    del x, y
+    torch.cuda.empty_cache()
+    return {"hbm_copy_GBs": 2 * 4 * n / t_copy / 1e9, "copy_bytes": 2 * 4 * n,
+            "bf16_gemm_TFLOPs": 2 * m ** 3 / t_gemm / 1e12, "gemm_shape": [m, m, m]}
+
+
+def _oracle_slice(args):
+    """One oracle process on its own slice of the chains (a worker of cpu_baseline_all_cores)."""
+    name, k, n_chains, n_unadj, n_adj = args
+    from oracle import oracle as orc
+    from paper_2601_16696_amd import workloads
+    w = getattr(workloads, name)()
+    lo = (k * n_chains) % w["n_chains"]
+    sub = dict(w)
+    sub["x0"] = np.asarray(w["x0"])[lo:lo + n_chains]
+    sub["n_chains"] = n_chains
+    t0 = time.perf_counter()
+    e = orc.Ensemble(orc.Target.from_workload(sub), n_chains, w["seed"] + k, switch_policy=1,
+                     max_steps_unadj=n_unadj, max_steps_total=n_unadj + 15 * n_adj)
+    e.init(sub["x0"])
+    e.step_unadjusted(n_unadj)
+    e.step_adjusted(n_adj)
+    return e.stats()["grads_per_chain"] * n_chains, time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(gen, n_chains=256, n_unadj=10, n_adj=1, procs=16):
+    """The oracle as it stands on all host cores: procs independent processes (a fresh interpreter each,
+    nothing of the GPU), each running the oracle on its own slice of n_chains chains with its own
+    ensemble statistics; throughput = all chain-gradients over the slowest process's time."""
+    import multiprocessing as mp
+    procs = max(1, min(procs, os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_slice, [(gen, k, n_chains, n_unadj, n_adj) for k in range(procs)])
+    grads = sum(r[0] for r in res)
+    t = max(r[1] for r in res)
+    return dict(value=grads / t, unit="chain-grad evals/s", cores=procs, kind="oracle",
+                sample=f"{procs} processes x {n_chains} chains (distinct slices of {gen}), init + {n_unadj} "
+                       f"unadjusted steps + {n_adj} MAMS transition each ({grads} chain-gradients, slowest process "
+                       f"{t:.1f} s, single-threaded FP64 per process)")
 
 
 CPU_SAMPLE = {  # about 10 s of single-threaded oracle work on the same workload
@@ -273,6 +341,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-bias", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured copy and GEMM peaks")
+    ap.add_argument("--full-rank-compare", type=int, default=0, metavar="P",
+                    help="also time the same runs with the full-rank loss from P probes and report the ratio")
+    ap.add_argument("--cpu-procs", type=int, default=16, help="oracle processes of the all-cores baseline (0: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -411,6 +483,24 @@ def main():
             "speedup_of_f32": (l64["ms"] / l32["ms"]) if l32.get("ms") and l64.get("ms") else None}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, **CPU_SAMPLE[args.workload])
+        if args.cpu_procs > 0:
+            line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(gen, procs=args.cpu_procs,
+                                                                    **CPU_SAMPLE[args.workload])
+    if args.full_rank_compare > 0:
+        rf = gpu_throughput(w, prec, args.steps, args.warmup, full_rank_probes=args.full_rank_compare)
+        del rf["sampler"]
+        line["full_rank_loss"] = {
+            "probes": args.full_rank_compare, "ms_per_step_diagonal": r["ms"], "ms_per_step_full_rank": rf["ms"],
+            "run_time_ratio": rf["ms"] / r["ms"],
+            "note": "section 'Equipartition condition' (full-rank form); the paper's Table 4 gives full-rank / "
+                    "diagonal run-time ratios of 0.95-1.10 on its targets (context only)"}
+    if not args.no_peaks:
+        pk = measured_peaks()
+        line["measured_peaks"] = pk
+        if roof["unit"] == "TFLOP/s" and roof["bound"] == "mfma" and prec == "bf16":
+            roof["frac_of_measured_peak"] = roof["achieved"] / pk["bf16_gemm_TFLOPs"]
+        elif roof["unit"] == "GB/s":
+            roof["frac_of_measured_peak"] = roof["achieved"] / pk["hbm_copy_GBs"]
     print(json.dumps(line))
 
 
