@@ -84,9 +84,10 @@ typedef enum { LAPS_F64 = 0, LAPS_F32 = 1, LAPS_MIXED_BF16 = 2 } laps_precision;
  *                    row-major, symmetric positive definite); LAPS_F64 or
  *                    LAPS_F32 state.
  * LAPS_LOGREG, LAPS_CALLBACK and LAPS_GAUSS_DENSE run through the per-chain
- * update kernels and are limited to d <= 128 (either adjusted integrator):
- * their wider update teams are switched off (LAPS_EUNSUPPORTED) after GPU
- * faults whose cause is not found.
+ * update kernels (teams of at most 16 lanes, several octs per lane above
+ * d = 128): LAPS_CALLBACK and LAPS_GAUSS_DENSE up to d = 512, LAPS_LOGREG up
+ * to d = 128, where its matrix-core gradient kernels stop; larger d gives
+ * LAPS_EUNSUPPORTED.
  * Target data must stay valid and unchanged while a context uses it. */
 typedef enum {
   LAPS_GAUSS_DIAG = 0,

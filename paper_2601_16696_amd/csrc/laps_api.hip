@@ -85,9 +85,11 @@ struct Shape {
 };
 
 // Largest dimension of the targets run by the per-chain update kernels
-// (logistic regression, callbacks, the dense Gaussian): one oct per lane in
-// teams of up to 16 lanes.
-constexpr int64_t kUpdateMaxD = 128;
+// (callbacks, the dense Gaussian): teams of at most 16 lanes with up to 4 octs
+// per lane.  Logistic regression stops at 128, where its matrix-core gradient
+// kernels hold theta and the gradient tiles of a chain in registers.
+constexpr int64_t kUpdateMaxD = 512;
+constexpr int64_t kLogregMaxD = 128;
 
 bool is_local(int kind) { return kind == LAPS_GAUSS_DIAG || kind == LAPS_STOCHVOL || kind == LAPS_PHI4; }
 
@@ -163,19 +165,20 @@ bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
   if (is_local(tg->kind))
     return local_shape(tg->kind, dbl, cfg->n_chains, cfg->d, cfg->team_lanes, s, cfg->block_threads);
   if (tg->kind == LAPS_LOGREG || tg->kind == LAPS_CALLBACK || tg->kind == LAPS_GAUSS_DENSE) {
-    // per-chain update kernels: one oct per lane, up to 64 lanes
+    // per-chain update kernels: one oct per lane in teams of up to 16 lanes,
+    // then 16-lane teams with Q = 2..4 octs per lane
     const int64_t octs = (cfg->d + 7) / 8;
     if (cfg->d > kUpdateMaxD) return false;
     int T = 1;
-    while (T < octs) T <<= 1;
+    while (T < octs && T < 16) T <<= 1;
     s.T = T;
-    s.Q = 1;
+    s.Q = (int)((octs + T - 1) / T);
     s.block = cfg->block_threads > 0 ? cfg->block_threads : 256;  // 64, 128 or 256 >= T
     s.tpw = s.block / T;
     s.G = (int)((cfg->n_chains + s.tpw - 1) / s.tpw);
     s.grid_full = s.G;
     s.split = false;
-    s.shmem = 2 * kRedSlots * sizeof(double) + (size_t)4 * 8 * T * 8;
+    s.shmem = 2 * kRedSlots * sizeof(double) + (size_t)4 * 8 * T * s.Q * 8;
     s.shmem_sig = s.shmem;
     s.nb = (int)((cfg->d + fin_dims(cfg->d) - 1) / fin_dims(cfg->d));
     return true;
@@ -295,14 +298,16 @@ laps_status validate(const laps_config *cfg, const laps_target *tg, std::string 
       if (tg->kind == LAPS_GAUSS_DENSE && !tg->data[0]) return why = "a dense Gaussian needs data[0] = A", LAPS_EINVAL;
       if (tg->kind != LAPS_LOGREG && cfg->prec == LAPS_MIXED_BF16)
         return why = "callback and dense Gaussian targets run in LAPS_F64 or LAPS_F32", LAPS_EUNSUPPORTED;
-      // These targets share the per-chain update kernels.  Two GPU runs that used their 32- and 64-lane
-      // teams (d > 128) outside the initialisation faulted the GPU with no cause shown, so those teams are
-      // refused until one is.  With teams of at most 16 lanes the staged MN4 transition runs the same
-      // device code as MN2 (only the stage count and the host-supplied coefficients differ).
-      if (cfg->d > kUpdateMaxD)
-        return why = "logistic-regression, callback and dense Gaussian targets support d <= 128 (their 32- and "
-                     "64-lane update teams are switched off)",
+      // These targets share the per-chain update kernels.  Two GPU runs that used 32- and 64-lane update
+      // teams (d > 128) outside the initialisation faulted the GPU with no cause shown; those teams are no
+      // longer built: above 16 octs a 16-lane team holds several octs per lane.  The staged MN4 transition
+      // runs the same device code as MN2 (only the stage count and the host-supplied coefficients differ).
+      if (tg->kind == LAPS_LOGREG && cfg->d > kLogregMaxD)
+        return why = "logistic regression supports d <= 128 (its matrix-core gradient kernels hold a chain's "
+                     "theta and gradient tiles in registers)",
                LAPS_EUNSUPPORTED;
+      if (cfg->d > kUpdateMaxD)
+        return why = "callback and dense Gaussian targets support d <= 512", LAPS_EUNSUPPORTED;
       break;
     default:
       return why = "unknown target kind", LAPS_EINVAL;
@@ -494,7 +499,7 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     a.ca0 = C.a[0];
     a.cbk = k + 1 < 6 ? C.b[k + 1] : 0.0;
     a.cak = k + 1 < 5 ? C.a[k + 1] : 0.0;
-    return launch_logreg_update(prec, a, c->G, c->block, c->shmem, c->stream);
+    return launch_logreg_update(prec, c->Q, a, c->G, c->block, c->shmem, c->stream);
   };
   const bool cb = c->tg.kind == LAPS_CALLBACK;
   int cb_rc = 0;
@@ -873,7 +878,7 @@ extern "C" laps_status laps_eval(laps_ctx *c, const void *x_dev, void *logp_dev,
     a.mode = LR_EVAL;
     a.logp_out = static_cast<double *>(logp_dev);
     a.g_out = grad_dev;
-    e = launch_logreg_update(prec, a, c->G, c->block, c->shmem, c->stream);
+    e = launch_logreg_update(prec, c->Q, a, c->G, c->block, c->shmem, c->stream);
   }
   return e == hipSuccess ? LAPS_OK : fail(c, e, "evaluation");
 }

@@ -173,7 +173,9 @@ __host__ __device__ inline LrOffsets logreg_layout(int prec, int64_t n, int64_t 
 void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int wgs, int &S, int &NB, int &bps);
 hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s);
 hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s);
-hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, int block, size_t shmem, hipStream_t s);
+// Q octs per lane (1..4) in teams of a.T <= 16 lanes.
+hipError_t launch_logreg_update(int prec, int Q, const LogregArgs &a, int grid, int block, size_t shmem,
+                                hipStream_t s);
 // Dense-precision Gaussian: the precision matrix copied in the state type
 // after the single partial-sum split of the scratch, and its gradient kernel.
 hipError_t launch_dense_pack(int prec, const LogregArgs &a, hipStream_t s);

@@ -539,73 +539,93 @@ __global__ void __launch_bounds__(256) k_lr_grad_f64_mfma(LogregArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// per-chain update kernels (one team of T <= 64 lanes per chain, 256 threads)
+// per-chain update kernels: one team of T <= 16 lanes per chain (64, 128 or
+// 256 threads), lane r holding the Q octs r + q T (q < Q) of the chain
 // ---------------------------------------------------------------------------
-template <class Real>
+template <class Real, int Q>
 __device__ __forceinline__ void lr_grad_sum(const LogregArgs &a, const LrOffsets &off, int64_t m, int r, int T,
-                                            bool act, const Real (&x)[1][8], Real (&g)[1][8], double &lps) {
+                                            bool act, const Real (&x)[Q][8], Real (&g)[Q][8], double &lps) {
   const Real *Gp = reinterpret_cast<const Real *>(a.scratch + off.Gp);
   const double *lp = reinterpret_cast<const double *>(a.scratch + off.lp);
-  const int64_t e0 = 8 * (int64_t)r;
-  Real acc[8] = {};
+  Real acc[Q][8] = {};
   lps = 0.0;
   // splits in order, four at a time: the four loads are issued before the
   // first of them is used, so the split sum costs ~S/4 memory latencies
   const int S = act ? a.S : 0;
-  const bool mine = e0 < a.d;
+  bool mine[Q];
+  int64_t e0[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    e0[q] = 8 * (int64_t)(r + q * T);
+    mine[q] = e0[q] < a.d;
+  }
   int s = 0;
   for (; s + 4 <= S; s += 4) {
-    Real v[4][8];
+    Real v[4][Q][8];
     double l[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (mine) ld8<Real>(Gp + ((int64_t)(s + k) * a.N + m) * a.ld + e0, v[k]);
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (mine[q]) ld8<Real>(Gp + ((int64_t)(s + k) * a.N + m) * a.ld + e0[q], v[k][q]);
       l[k] = lp[(int64_t)(s + k) * a.N + m];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (mine)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] += v[k][i];
+      for (int q = 0; q < Q; ++q)
+        if (mine[q])
+#pragma unroll
+          for (int i = 0; i < 8; ++i) acc[q][i] += v[k][q][i];
       lps += l[k];
     }
   }
   for (; s < S; ++s) {
-    Real v[8];
-    if (mine) {
-      ld8<Real>(Gp + ((int64_t)s * a.N + m) * a.ld + e0, v);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] += v[i];
-    }
+    for (int q = 0; q < Q; ++q)
+      if (mine[q]) {
+        Real v[8];
+        ld8<Real>(Gp + ((int64_t)s * a.N + m) * a.ld + e0[q], v);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[q][i] += v[i];
+      }
     lps += lp[(int64_t)s * a.N + m];
   }
 #pragma unroll
-  for (int i = 0; i < 8; ++i) g[0][i] = (e0 + i < a.d) ? acc[i] - (a.prior ? x[0][i] : Real(0)) : Real(0);
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      g[q][i] = (e0[q] + i < a.d) ? acc[q][i] - (a.prior ? x[q][i] : Real(0)) : Real(0);
 }
 
 // The lane's share of the log-density terms that depend on theta alone: the
 // N(0, I) prior -|theta|^2 / 2 and, for the bf16 gradient (whose split sums
 // leave it out), sum_n (y_n - 1/2) z_n = theta . (X^T (y - 1/2)) in FP64.
-template <class Real>
-__device__ __forceinline__ double lr_theta_terms(const LogregArgs &a, const LrOffsets &off, int r,
-                                                 const Real (&x)[1][8]) {
+template <class Real, int Q>
+__device__ __forceinline__ double lr_theta_terms(const LogregArgs &a, const LrOffsets &off, int r, int T,
+                                                 const Real (&x)[Q][8]) {
   double v = 0.0;
   if (a.prior) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v -= 0.5 * (double)x[0][i] * (double)x[0][i];
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v -= 0.5 * (double)x[q][i] * (double)x[q][i];
   }
   if (a.wy_term) {
-    const int64_t e0 = 8 * (int64_t)r;
-    if (e0 < a.d) {
-      const double *wy = reinterpret_cast<const double *>(a.scratch + off.wy) + e0;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v += (double)x[0][i] * wy[i];
+    for (int q = 0; q < Q; ++q) {
+      const int64_t e0 = 8 * (int64_t)(r + q * T);
+      if (e0 < a.d) {
+        const double *wy = reinterpret_cast<const double *>(a.scratch + off.wy) + e0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v += (double)x[q][i] * wy[i];
+      }
     }
   }
   return v;
 }
 
-template <class Real>
+template <class Real, int Q>
 __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   if (!lr_gate(a)) return;
   extern __shared__ double smem[];
@@ -629,129 +649,143 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   const double eps = H->eps;
   const uint64_t t = (uint64_t)H->t;
   const double h = 0.5 * eps;
-  Real x[1][8], u[1][8], g[1][8], z[1][8];
-  load_row<Real, 1>(X + m * ld, r, T, d, act, x);
+  Real x[Q][8], u[Q][8], g[Q][8], z[Q][8];
+  load_row<Real, Q>(X + m * ld, r, T, d, act, x);
   const int mode = a.mode;
 
   if (mode == LR_EVAL) {
     // log p and gradient at the caller's positions (a.x): split sums plus the prior
     double lps;
-    lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
-    double v[1] = {lr_theta_terms<Real>(a, off, r, x)};
+    lr_grad_sum<Real, Q>(a, off, m, r, T, act, x, g, lps);
+    double v[1] = {lr_theta_terms<Real, Q>(a, off, r, T, x)};
     team_sum<1>(v, T, red, slot);
     if (act) {
-      if (a.g_out) store_row<Real, 1>(static_cast<Real *>(a.g_out) + m * ld, r, T, d, g);
+      if (a.g_out) store_row<Real, Q>(static_cast<Real *>(a.g_out) + m * ld, r, T, d, g);
       if (r == 0) a.logp_out[m] = lps + v[0];
     }
     return;
   }
 
   if (mode == LR_INIT || mode == LR_POST) {
-    double S[4][1][8] = {};
+    double S[4][Q][8] = {};
     // every global load of this stage is issued before the first dependent use
-    double K[1][8];
+    double K[Q][8];
     if (mode == LR_POST) {
-      load_shift<1>(a.shiftK, r, T, d, K);
-      load_row<Real, 1>(U + m * ld, r, T, d, act, u);
+      load_shift<Q>(a.shiftK, r, T, d, K);
+      load_row<Real, Q>(U + m * ld, r, T, d, act, u);
     }
     double lps;
-    lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
+    lr_grad_sum<Real, Q>(a, off, m, r, T, act, x, g, lps);
     if (mode == LR_INIT) {
-      lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, 0, TAG_INIT_DIR, 0, z);
-      double v[3] = {lr_theta_terms<Real>(a, off, r, x), 0.0, 0.0};
+      lane_normals<Real, Q>(a.seed, (uint64_t)m, r, T, d, 0, TAG_INIT_DIR, 0, z);
+      double v[3] = {lr_theta_terms<Real, Q>(a, off, r, T, x), 0.0, 0.0};
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        v[1] += (double)g[0][i] * (double)g[0][i];
-        v[2] += (double)z[0][i] * (double)z[0][i];
-      }
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          v[1] += (double)g[q][i] * (double)g[q][i];
+          v[2] += (double)z[q][i] * (double)z[q][i];
+        }
       team_sum<3>(v, T, red, slot);
       const double l1 = lps + v[0];
       if (a.u0) {
-        load_row<Real, 1>(static_cast<const Real *>(a.u0) + m * ld, r, T, d, act, u);
+        load_row<Real, Q>(static_cast<const Real *>(a.u0) + m * ld, r, T, d, act, u);
       } else {
         const double gn = sqrt(v[1]);
         const bool useg = gn > 0.0 && isfinite(gn);
         const Real scl = (Real)(1.0 / (useg ? gn : sqrt(v[2])));
 #pragma unroll
-        for (int i = 0; i < 8; ++i) u[0][i] = (useg ? g[0][i] : z[0][i]) * scl;
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) u[q][i] = (useg ? g[q][i] : z[q][i]) * scl;
       }
       if (act) {
-        store_row<Real, 1>(X + m * ld, r, T, d, x);
-        store_row<Real, 1>(U + m * ld, r, T, d, u);
-        store_row<Real, 1>(Gc + m * ld, r, T, d, g);
+        store_row<Real, Q>(X + m * ld, r, T, d, x);
+        store_row<Real, Q>(U + m * ld, r, T, d, u);
+        store_row<Real, Q>(Gc + m * ld, r, T, d, g);
         if (r == 0) {
           a.logp[m] = l1;
           a.delta[m] = 0.0;
           a.acc[m] = 0.0;
         }
-        const double K0[1][8] = {};
-        accumulate_stats<Real, 1>(S, K0, x, g);
+        const double K0[Q][8] = {};
+        accumulate_stats<Real, Q>(S, K0, x, g);
       }
     } else {
       const double Lm = H->L;
       const Real c1 = (Real)exp(-h / Lm), c2 = (Real)(sqrt(-expm1(-2.0 * h / Lm)) / sqrt((double)d));
-      double v[3] = {lr_theta_terms<Real>(a, off, r, x), 0.0, 0.0};
+      double v[3] = {lr_theta_terms<Real, Q>(a, off, r, T, x), 0.0, 0.0};
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        v[1] += (double)g[0][i] * (double)g[0][i];
-        v[2] += (double)g[0][i] * (double)u[0][i];
-      }
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          v[1] += (double)g[q][i] * (double)g[q][i];
+          v[2] += (double)g[q][i] * (double)u[q][i];
+        }
       team_sum<3>(v, T, red, slot);
       const double l1 = lps + v[0];
       const BMap b2 = b_map_dyn<Real>(a.dyn, v[1], v[2], h, dm1);
-      lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, 0, z);
+      lane_normals<Real, Q>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, 0, z);
       double w1[1] = {0.0};
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const Real w = c1 * ((Real)b2.A * u[0][i] + (Real)b2.Bg * g[0][i]) + c2 * z[0][i];
-        u[0][i] = w;
-        w1[0] += (double)w * (double)w;
-      }
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const Real w = c1 * ((Real)b2.A * u[q][i] + (Real)b2.Bg * g[q][i]) + c2 * z[q][i];
+          u[q][i] = w;
+          w1[0] += (double)w * (double)w;
+        }
       team_sum<1>(w1, T, red, slot);
       const Real inw = (Real)refresh_scale(a.dyn, w1[0]);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) u[0][i] *= inw;
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) u[q][i] *= inw;
       if (act) {
-        store_row<Real, 1>(U + m * ld, r, T, d, u);
-        store_row<Real, 1>(Gc + m * ld, r, T, d, g);
+        store_row<Real, Q>(U + m * ld, r, T, d, u);
+        store_row<Real, Q>(Gc + m * ld, r, T, d, g);
         if (r == 0) {
           a.logp[m] = l1;
           a.delta[m] = (sc_l0[m] - l1) + sc_dk[m] + b2.dK;
         }
-        accumulate_stats<Real, 1>(S, K, x, g);
+        accumulate_stats<Real, Q>(S, K, x, g);
       }
     }
-    write_partials<Real, 1>(a.partials, d, ld, S, red + 2 * kRedSlots, T, r);
+    write_partials<Real, Q>(a.partials, d, ld, S, red + 2 * kRedSlots, T, r);
     return;
   }
 
   if (mode == LR_PRE) {
     const double Lm = H->L;
     const Real c1 = (Real)exp(-h / Lm), c2 = (Real)(sqrt(-expm1(-2.0 * h / Lm)) / sqrt((double)d));
-    load_row<Real, 1>(U + m * ld, r, T, d, act, u);
-    load_row<Real, 1>(Gc + m * ld, r, T, d, act, g);
-    lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_FIRST, 0, z);
+    load_row<Real, Q>(U + m * ld, r, T, d, act, u);
+    load_row<Real, Q>(Gc + m * ld, r, T, d, act, g);
+    lane_normals<Real, Q>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_FIRST, 0, z);
     double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const Real w = c1 * u[0][i] + c2 * z[0][i];
-      u[0][i] = w;
-      v[0] += (double)w * (double)w;
-      v[1] += (double)g[0][i] * (double)w;
-      v[2] += (double)g[0][i] * (double)g[0][i];
-    }
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const Real w = c1 * u[q][i] + c2 * z[q][i];
+        u[q][i] = w;
+        v[0] += (double)w * (double)w;
+        v[1] += (double)g[q][i] * (double)w;
+        v[2] += (double)g[q][i] * (double)g[q][i];
+      }
     team_sum<3>(v, T, red, slot);
     const double inw = refresh_scale(a.dyn, v[0]);
     const BMap b1 = b_map_dyn<Real>(a.dyn, v[2], v[1] * inw, h, dm1);
     const Real A1 = (Real)(b1.A * inw), B1 = (Real)b1.Bg, epsR = (Real)eps;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      u[0][i] = A1 * u[0][i] + B1 * g[0][i];
-      x[0][i] += epsR * u[0][i];
-    }
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        u[q][i] = A1 * u[q][i] + B1 * g[q][i];
+        x[q][i] += epsR * u[q][i];
+      }
     if (act) {
-      store_row<Real, 1>(X + m * ld, r, T, d, x);
-      store_row<Real, 1>(U + m * ld, r, T, d, u);
+      store_row<Real, Q>(X + m * ld, r, T, d, x);
+      store_row<Real, Q>(U + m * ld, r, T, d, u);
       if (r == 0) {
         sc_l0[m] = a.logp[m];
         sc_dk[m] = b1.dK;
@@ -763,54 +797,62 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   // adjusted phase: preconditioned MAMS trajectory, one stage per launch
   const double Lp = a.Lp_factor * (double)a.n_traj * eps;
   const Real c1 = (Real)exp(-h / Lp), c2 = (Real)(sqrt(-expm1(-2.0 * h / Lp)) / sqrt((double)d));
-  Real sg[1][8];
-  load_row<Real, 1>(static_cast<const Real *>(a.sigma), r, T, d, true, sg);
+  Real sg[Q][8];
+  load_row<Real, Q>(static_cast<const Real *>(a.sigma), r, T, d, true, sg);
   double D = 0.0, lprev = 0.0;
 
   // first half of a step: O_{eps/2}(j), B_{b0 eps}, A_{a0 eps}
   auto step_start = [&](int j) {
-    lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_FIRST, (uint32_t)j, z);
+    lane_normals<Real, Q>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_FIRST, (uint32_t)j, z);
     double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const Real w = c1 * u[0][i] + c2 * z[0][i];
-      const Real gt = sg[0][i] * g[0][i];
-      u[0][i] = w;
-      v[0] += (double)w * (double)w;
-      v[1] += (double)gt * (double)w;
-      v[2] += (double)gt * (double)gt;
-    }
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const Real w = c1 * u[q][i] + c2 * z[q][i];
+        const Real gt = sg[q][i] * g[q][i];
+        u[q][i] = w;
+        v[0] += (double)w * (double)w;
+        v[1] += (double)gt * (double)w;
+        v[2] += (double)gt * (double)gt;
+      }
     team_sum<3>(v, T, red, slot);
     const double inw = refresh_scale(a.dyn, v[0]);
     const BMap b = b_map_dyn<Real>(a.dyn, v[2], v[1] * inw, a.cb0 * eps, dm1);
     D += b.dK;
     const Real Ab = (Real)(b.A * inw), Bb = (Real)b.Bg, ha = (Real)(a.ca0 * eps);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      u[0][i] = Ab * u[0][i] + Bb * sg[0][i] * g[0][i];
-      x[0][i] += ha * sg[0][i] * u[0][i];
-    }
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        u[q][i] = Ab * u[q][i] + Bb * sg[q][i] * g[q][i];
+        x[q][i] += ha * sg[q][i] * u[q][i];
+      }
   };
 
   if (mode == LR_MBEGIN) {
-    load_row<Real, 1>(Gc + m * ld, r, T, d, act, g);
+    load_row<Real, Q>(Gc + m * ld, r, T, d, act, g);
     if (act) {
-      store_row<Real, 1>(X0 + m * ld, r, T, d, x);
-      store_row<Real, 1>(G0 + m * ld, r, T, d, g);
+      store_row<Real, Q>(X0 + m * ld, r, T, d, x);
+      store_row<Real, Q>(G0 + m * ld, r, T, d, g);
     }
     const double l0 = act ? a.logp[m] : 0.0;
-    lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_FULL_REFRESH, 0, z);
+    lane_normals<Real, Q>(a.seed, (uint64_t)m, r, T, d, t, TAG_FULL_REFRESH, 0, z);
     double v1[1] = {0.0};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v1[0] += (double)z[0][i] * (double)z[0][i];
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v1[0] += (double)z[q][i] * (double)z[q][i];
     team_sum<1>(v1, T, red, slot);
     const Real iz = (Real)full_refresh_scale(a.dyn, v1[0], d);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) u[0][i] = z[0][i] * iz;
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[q][i] = z[q][i] * iz;
     step_start(0);
     if (act) {
-      store_row<Real, 1>(X + m * ld, r, T, d, x);
-      store_row<Real, 1>(U + m * ld, r, T, d, u);
+      store_row<Real, Q>(X + m * ld, r, T, d, x);
+      store_row<Real, Q>(U + m * ld, r, T, d, u);
       if (r == 0) {
         sc_l0[m] = l0;
         sc_lprev[m] = l0;
@@ -821,16 +863,18 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   }
 
   // LR_MSTEP: consume gradient k of step j
-  load_row<Real, 1>(U + m * ld, r, T, d, act, u);
+  load_row<Real, Q>(U + m * ld, r, T, d, act, u);
   double lps;
-  lr_grad_sum<Real>(a, off, m, r, T, act, x, g, lps);
-  double v[3] = {lr_theta_terms<Real>(a, off, r, x), 0.0, 0.0};
+  lr_grad_sum<Real, Q>(a, off, m, r, T, act, x, g, lps);
+  double v[3] = {lr_theta_terms<Real, Q>(a, off, r, T, x), 0.0, 0.0};
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const Real gt = sg[0][i] * g[0][i];
-    v[1] += (double)gt * (double)gt;
-    v[2] += (double)gt * (double)u[0][i];
-  }
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const Real gt = sg[q][i] * g[q][i];
+      v[1] += (double)gt * (double)gt;
+      v[2] += (double)gt * (double)u[q][i];
+    }
   team_sum<3>(v, T, red, slot);
   const double lnew = lps + v[0];
   D = (act ? sc_D[m] + (sc_lprev[m] - lnew) : 0.0);
@@ -841,25 +885,33 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     D += b.dK;
     const Real Ab = (Real)b.A, Bb = (Real)b.Bg;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) u[0][i] = Ab * u[0][i] + Bb * sg[0][i] * g[0][i];
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[q][i] = Ab * u[q][i] + Bb * sg[q][i] * g[q][i];
   }
   if (k + 1 < a.cK - 1) {
     const Real ha = (Real)(a.cak * eps);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x[0][i] += ha * sg[0][i] * u[0][i];
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) x[q][i] += ha * sg[q][i] * u[q][i];
   } else {
-    lane_normals<Real, 1>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, (uint32_t)j, z);
+    lane_normals<Real, Q>(a.seed, (uint64_t)m, r, T, d, t, TAG_O_SECOND, (uint32_t)j, z);
     double w1[1] = {0.0};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const Real w = c1 * u[0][i] + c2 * z[0][i];
-      u[0][i] = w;
-      w1[0] += (double)w * (double)w;
-    }
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const Real w = c1 * u[q][i] + c2 * z[q][i];
+        u[q][i] = w;
+        w1[0] += (double)w * (double)w;
+      }
     team_sum<1>(w1, T, red, slot);
     const Real inw = (Real)refresh_scale(a.dyn, w1[0]);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) u[0][i] *= inw;
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[q][i] *= inw;
     if (j + 1 < a.n_traj) {
       step_start(j + 1);
     } else {
@@ -871,15 +923,15 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
       const bool accept = !nanD && (U01 < wacc);
       if (act) {
         if (accept) {
-          store_row<Real, 1>(X + m * ld, r, T, d, x);
-          store_row<Real, 1>(Gc + m * ld, r, T, d, g);
+          store_row<Real, Q>(X + m * ld, r, T, d, x);
+          store_row<Real, Q>(Gc + m * ld, r, T, d, g);
           if (r == 0) a.logp[m] = lnew;
         } else {
-          Real x0[1][8], g0[1][8];
-          load_row<Real, 1>(X0 + m * ld, r, T, d, true, x0);
-          load_row<Real, 1>(G0 + m * ld, r, T, d, true, g0);
-          store_row<Real, 1>(X + m * ld, r, T, d, x0);
-          store_row<Real, 1>(Gc + m * ld, r, T, d, g0);
+          Real x0[Q][8], g0[Q][8];
+          load_row<Real, Q>(X0 + m * ld, r, T, d, true, x0);
+          load_row<Real, Q>(G0 + m * ld, r, T, d, true, g0);
+          store_row<Real, Q>(X + m * ld, r, T, d, x0);
+          store_row<Real, Q>(Gc + m * ld, r, T, d, g0);
           if (r == 0) a.logp[m] = sc_l0[m];
         }
         if (r == 0) {
@@ -891,9 +943,9 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     }
   }
   if (act) {
-    store_row<Real, 1>(X + m * ld, r, T, d, x);
-    store_row<Real, 1>(U + m * ld, r, T, d, u);
-    store_row<Real, 1>(Gc + m * ld, r, T, d, g);
+    store_row<Real, Q>(X + m * ld, r, T, d, x);
+    store_row<Real, Q>(U + m * ld, r, T, d, u);
+    store_row<Real, Q>(Gc + m * ld, r, T, d, g);
     if (r == 0) {
       sc_D[m] = D;
       sc_lprev[m] = lprev;
@@ -947,11 +999,15 @@ hipError_t launch_logreg_grad(int prec, const LogregArgs &a, hipStream_t s) {
   return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, dim3(512), args, 0, s);
 }
 
-hipError_t launch_logreg_update(int prec, const LogregArgs &a, int grid, int block, size_t shmem, hipStream_t s) {
-  if (prec == 0)
-    hipLaunchKernelGGL(k_lr_update<double>, dim3(grid), dim3(block), shmem, s, a);
-  else
-    hipLaunchKernelGGL(k_lr_update<float>, dim3(grid), dim3(block), shmem, s, a);
+hipError_t launch_logreg_update(int prec, int Q, const LogregArgs &a, int grid, int block, size_t shmem,
+                                hipStream_t s) {
+  typedef void (*Fn)(LogregArgs);
+  static const Fn fd[4] = {k_lr_update<double, 1>, k_lr_update<double, 2>, k_lr_update<double, 3>,
+                           k_lr_update<double, 4>};
+  static const Fn ff[4] = {k_lr_update<float, 1>, k_lr_update<float, 2>, k_lr_update<float, 3>,
+                           k_lr_update<float, 4>};
+  if (Q < 1 || Q > 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((prec == 0 ? fd : ff)[Q - 1], dim3(grid), dim3(block), shmem, s, a);
   return hipGetLastError();
 }
 

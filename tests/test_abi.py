@@ -145,9 +145,10 @@ def test_team_shape_override(L, kind, d, side, lanes, ok):
 @pytest.mark.parametrize("kind", [1, 4, 5])
 def test_update_kernel_targets_limited_to_narrow_teams(L, kind):
     """Logistic regression, callbacks and the dense Gaussian share the
-    per-chain update kernels.  Their 32- and 64-lane teams (d > 128) are
-    refused until the GPU faults seen with them are explained, whatever the
-    integrator; d <= 128 is accepted with MN2 and with MN4."""
+    per-chain update kernels, whose teams have at most 16 lanes (several octs
+    per lane above d = 128, up to d = 512).  Logistic regression stops at
+    d = 128 (its gradient kernels hold a chain's theta in registers); both
+    integrators are accepted."""
     def cfg(d, integ=0):
         c, t = _cfg_target(L, kind=kind, d=d)
         t.cb = 0x3000
@@ -155,9 +156,12 @@ def test_update_kernel_targets_limited_to_narrow_teams(L, kind):
         return c, t
     assert _ws(L, *cfg(100))[0] == L.OK
     assert _ws(L, *cfg(128))[0] == L.OK
-    for d in (129, 138, 200, 204, 300):
+    for d in (129, 138, 200, 204, 300, 512):
         for integ in (0, 1, 2):
-            assert _ws(L, *cfg(d, integ))[0] == L.EUNSUPPORTED, (d, integ)
+            want = L.EUNSUPPORTED if kind == L.LOGREG else L.OK
+            assert _ws(L, *cfg(d, integ))[0] == want, (d, integ)
+    for integ in (0, 1, 2):
+        assert _ws(L, *cfg(513, integ))[0] == L.EUNSUPPORTED
     for d in (37, 100, 128):
         assert _ws(L, *cfg(d, 2))[0] == L.OK, d
 

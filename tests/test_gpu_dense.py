@@ -32,9 +32,8 @@ def _rel_rows(a, b):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
-# d = 203 needs the 32-lane update teams, which the library refuses after GPU faults whose cause is not found
-SHAPES = [(70, 37), (64, 100), (130, 16),
-          pytest.param(40, 203, marks=pytest.mark.skip(reason="d > 128: 32/64-lane update teams switched off"))]
+# d = 203 and 300 run 16-lane update teams with 2 and 3 octs per lane
+SHAPES = [(70, 37), (64, 100), (130, 16), (40, 203), (24, 300)]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -63,7 +62,7 @@ def test_initial_gradient_and_logp(gpu, orc, prec, N, d):
 
 @pytest.mark.parametrize("integ", [1, 2])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("N,d", [(70, 37), (64, 100)])
+@pytest.mark.parametrize("N,d", [(70, 37), (64, 100), (40, 203), (24, 300)])
 def test_steps_and_transitions(gpu, orc, prec, N, d, integ):
     """Unadjusted steps and MAMS transitions with MN2 (integ 1) and MN4
     (integ 2) against the oracle.  FP32 positions after the transitions are
