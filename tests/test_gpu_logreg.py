@@ -43,10 +43,11 @@ def _rel_rows(a, b):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
-# d > 128 runs the per-chain update kernels with 32- or 64-lane teams, which the library refuses (and
-# the refusal is tested on the CPU in test_abi.py) after two GPU faults whose cause is not found
-WIDE = pytest.mark.skip(reason="d > 128 needs the 32/64-lane update teams, switched off after GPU faults "
-                               "whose cause is not found; the library refuses these shapes")
+# Logistic regression above d = 128 is refused by the library (its gradient kernels hold a chain's theta
+# in registers up to 128 coordinates; the refusal is tested on the CPU in test_abi.py).  These shapes also
+# ran in the two GPU faults whose cause is not found, so they stay off the GPU.
+WIDE = pytest.mark.skip(reason="logistic regression with d > 128 is refused by the library; these shapes ran in "
+                               "GPU faults whose cause is not found")
 
 
 @pytest.mark.parametrize("shape", [(100, 300, 37), (64, 32, 100), (130, 5000, 100),
@@ -240,8 +241,8 @@ def test_mixed_transitions_against_oracle_on_identical_states(gpu, orc, shape):
 @pytest.mark.parametrize("shape", [
     (40, 150, 100), (70, 300, 37),
     pytest.param((40, 150, 204), marks=pytest.mark.skip(
-        reason="the logistic-regression MN4 transition at d = 204 (32-lane update teams) faulted the GPU "
-               "(illegal memory access) with no cause shown yet; the library refuses d > 128"))])
+        reason="the logistic-regression MN4 transition at d = 204 faulted the GPU (illegal memory access) with "
+               "no cause shown; the library refuses logistic regression with d > 128"))])
 def test_fourth_order_transitions(gpu, orc, prec, shape):
     """The MN4 integrator in the adjusted phase (the automatic choice above
     d = 200, asked for explicitly here): five gradient stages per step
