@@ -44,7 +44,7 @@ struct laps_ctx {
   std::vector<hipEvent_t> log_ev;
   size_t log_used = 0;
   ~laps_ctx() {
-    for (hipEvent_t e : log_ev) hipEventDestroy(e);
+    for (hipEvent_t e : log_ev) (void)hipEventDestroy(e);
   }
 };
 
@@ -727,7 +727,7 @@ extern "C" laps_status laps_init_static(const laps_config *cfg, const laps_targe
     g_scratch_ptr[dev] = reinterpret_cast<void *>(((uintptr_t)p + 255) & ~(uintptr_t)255);
   }
   laps_ctx *c = &g_static_ctx[dev];
-  for (hipEvent_t v : c->log_ev) hipEventDestroy(v);
+  for (hipEvent_t v : c->log_ev) (void)hipEventDestroy(v);
   c->log_ev.clear();
   c->log_which = 0;
   c->log_every = 1;
@@ -927,13 +927,13 @@ extern "C" laps_status laps_graph_create(laps_ctx *const *ctxs, int32_t n_ctx, i
   if (e != hipSuccess) return fail(nullptr, e, "graph stream");
   std::vector<hipEvent_t> ev;
   auto cleanup = [&]() {
-    for (hipEvent_t v : ev) hipEventDestroy(v);
-    hipStreamDestroy(origin);
+    for (hipEvent_t v : ev) (void)hipEventDestroy(v);
+    (void)hipStreamDestroy(origin);
   };
   hipEvent_t fork;
   e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
   if (e != hipSuccess) {
-    hipStreamDestroy(origin);
+    (void)hipStreamDestroy(origin);
     return fail(nullptr, e, "graph events");
   }
   ev.push_back(fork);
@@ -969,7 +969,7 @@ extern "C" laps_status laps_graph_create(laps_ctx *const *ctxs, int32_t n_ctx, i
   const hipError_t e_end = hipStreamEndCapture(origin, &g);
   if (e == hipSuccess) e = e_end;
   if (st != LAPS_OK || e != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     cleanup();
     if (st != LAPS_OK) return st;
     return fail(nullptr, e, "capture");
@@ -978,13 +978,13 @@ extern "C" laps_status laps_graph_create(laps_ctx *const *ctxs, int32_t n_ctx, i
   e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
   cleanup();
   if (e != hipSuccess) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return fail(nullptr, e, "graph instantiate");
   }
   laps_graph *G = new (std::nothrow) laps_graph{g, x};
   if (!G) {
-    hipGraphExecDestroy(x);
-    hipGraphDestroy(g);
+    (void)hipGraphExecDestroy(x);
+    (void)hipGraphDestroy(g);
     return LAPS_EINVAL;
   }
   *out = G;
@@ -999,8 +999,8 @@ extern "C" laps_status laps_graph_launch(laps_graph *G, void *stream) {
 
 extern "C" laps_status laps_graph_destroy(laps_graph *G) {
   if (!G) return LAPS_OK;
-  hipGraphExecDestroy(G->exec);
-  hipGraphDestroy(G->graph);
+  (void)hipGraphExecDestroy(G->exec);
+  (void)hipGraphDestroy(G->graph);
   delete G;
   return LAPS_OK;
 }
@@ -1061,8 +1061,8 @@ extern "C" laps_status laps_time_kernel(laps_ctx *c, int32_t which, int32_t n_re
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(c, e, "kernel timing");
   *avg_ms = ms / (float)n_reps;
   return LAPS_OK;
@@ -1073,7 +1073,7 @@ extern "C" laps_status laps_kernel_log(laps_ctx *c, int32_t which, int32_t capac
   if (which == LAPS_KERNEL_GRAD ? is_local(c->tg.kind) : (which != 0 && !is_local(c->tg.kind)))
     return LAPS_EUNSUPPORTED;
   LAPS_CHECK(c, hipStreamSynchronize(c->stream), "stream sync");
-  for (hipEvent_t e : c->log_ev) hipEventDestroy(e);
+  for (hipEvent_t e : c->log_ev) (void)hipEventDestroy(e);
   c->log_ev.clear();
   c->log_used = 0;
   c->log_which = 0;
@@ -1138,8 +1138,8 @@ extern "C" laps_status laps_time_gradient(laps_ctx *c, int32_t n_reps, float *av
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(c, e, "gradient timing");
   *avg_ms = ms / (float)n_reps;
   return LAPS_OK;
