@@ -394,17 +394,27 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
 // of this step and V_ij = -E[(x_i - xbar_i) g_j] from ensemble averages,
 //   D~ = (1/(P d)) sum_p |z_p + (1/N) sum_m (x_m - xbar)(g_m . z_p)|^2.
 // Probe entry i of z_p is 1 - 2b, b = bit i mod 64 of word (i mod 256) / 64 of
-// Philox block (p, i / 256, t, TAG_PROBE); probes are regenerated, never stored.
-// Three passes, every sum in a fixed order:
+// Philox block (p, i / 256, t, TAG_PROBE); only the probes' words are kept
+// (P ceil(d / 256) blocks per step), never the d x P probe matrix.
+// Four passes, every sum in a fixed order:
+//   k_probe_words:   the Philox words of every probe block, once per step
 //   k_probe_dots:    s[m][p] = g_m . z_p            (one thread per (m, p))
 //   k_probe_project: w_c[p][i] = sum over chunk c of (x_mi - xbar_i) s[m][p]
+//                    (chunks of 64 chains, so that d P NC threads share the work)
 //   k_probe_norms:   per block, sum of (z_pi + (1/N) sum_c w_c[p][i])^2
 // and the controller adds the block sums in order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t probe_bits(uint64_t seed, int64_t p, int64_t blk, uint64_t t, int word) {
-  uint64_t w[4] = {(uint64_t)p, (uint64_t)blk, t, (uint64_t)TAG_PROBE};
-  philox4x64_10(w, seed, 0);
-  return w[word];
+__global__ void __launch_bounds__(256) k_probe_words(CtlArgs c) {
+  const DevHyper *H = c.hyp;
+  if (H->phase != PH_UNADJ) return;
+  const int64_t nblk = (c.d + 255) / 256;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= c.probes * nblk) return;
+  const int64_t p = idx / nblk, blk = idx - p * nblk;
+  uint64_t w[4] = {(uint64_t)p, (uint64_t)blk, (uint64_t)H->t, (uint64_t)TAG_PROBE};
+  philox4x64_10(w, c.seed, 0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c.pZw[idx * 4 + k] = w[k];
 }
 
 template <class Real>
@@ -415,12 +425,12 @@ __global__ void __launch_bounds__(256) k_probe_dots(CtlArgs c) {
   const int64_t P = c.probes;
   if (idx >= c.N * P) return;
   const int64_t m = idx / P, p = idx - m * P;
-  const uint64_t t = (uint64_t)H->t;
+  const int64_t nblk = (c.d + 255) / 256;
   const Real *g = static_cast<const Real *>(c.g) + m * c.ld;
   double s = 0.0;
   for (int64_t b0 = 0; b0 < c.d; b0 += 256) {
-    uint64_t w[4] = {(uint64_t)p, (uint64_t)(b0 / 256), t, (uint64_t)TAG_PROBE};
-    philox4x64_10(w, c.seed, 0);
+    const uint64_t *zw = c.pZw + (p * nblk + b0 / 256) * 4;
+    const uint64_t w[4] = {zw[0], zw[1], zw[2], zw[3]};
     const int64_t e = (c.d - b0 < 256) ? c.d - b0 : 256;
     for (int64_t k = 0; k < e; k += 8) {
       Real gv[8];
@@ -476,7 +486,7 @@ __global__ void __launch_bounds__(256) k_probe_norms(CtlArgs c) {
     const int64_t p = idx / d, i = idx - p * d;
     double w = 0.0;
     for (int ch = 0; ch < c.NC; ++ch) w += c.pW[((int64_t)ch * P + p) * d + i];
-    const uint64_t word = probe_bits(c.seed, p, i / 256, (uint64_t)H->t, (int)((i & 255) >> 6));
+    const uint64_t word = c.pZw[(p * ((d + 255) / 256) + i / 256) * 4 + ((i & 255) >> 6)];
     const double z = ((word >> (i & 63)) & 1u) ? -1.0 : 1.0;
     const double r = z + w / (double)c.N;
     v = r * r;
@@ -489,8 +499,9 @@ __global__ void __launch_bounds__(256) k_probe_norms(CtlArgs c) {
 
 hipError_t launch_probes(const CtlArgs &c, hipStream_t s) {
   if (c.probes <= 0) return hipSuccess;
-  const int64_t nd = c.N * c.probes, dp = c.d * c.probes;
+  const int64_t nd = c.N * c.probes, dp = c.d * c.probes, nw = c.probes * ((c.d + 255) / 256);
   const dim3 g1((unsigned)((nd + 255) / 256)), g2((unsigned)((dp + 255) / 256), (unsigned)c.NC);
+  hipLaunchKernelGGL(k_probe_words, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, c);
   if (c.sigma_double) {
     hipLaunchKernelGGL(k_probe_dots<double>, g1, dim3(256), 0, s, c);
     hipLaunchKernelGGL(k_probe_project<double>, g2, dim3(256), 0, s, c);

@@ -38,3 +38,22 @@ def test_relative_column(gpu):
     rows = gpu._relative([dict(reached=True, grads_per_chain=200), dict(reached=False),
                           dict(reached=True, grads_per_chain=100)])
     assert [r["relative"] for r in rows] == [2.0, None, 1.0]
+
+
+def test_batched_sweep_equals_sequential_runs(gpu):
+    """The batched driver (configurations advancing together on their own
+    streams) gives exactly the sequential driver's results: each run is
+    deterministic and independent of the others."""
+    w = workloads.gaussian(n_chains=256, d=20, x0_scale=1.0)
+    base = dict(max_unadj=300, max_total=800)
+    specs = [dict(C=0.01), dict(alpha=1.0), dict(integrator_adj=2, acc_target=0.9),
+             dict(switch_policy=1, max_unadj=50), dict(which="avg"),
+             dict(unadjusted_only=True, max_total=100, stop_at_hit=False, eps_fixed=0.05)]
+    seq = [gpu.grads_to_bias(w, w["sigma2"], "f64", **dict(base, **sp)) for sp in specs]
+    bat = gpu.grads_to_bias_many([dict(w=w, s2=w["sigma2"], **dict(base, **sp)) for sp in specs], "f64",
+                                 concurrent=4)
+    assert len(bat) == len(seq)
+    for a, b in zip(seq, bat):
+        for key in ("reached", "min_b2", "final_eps", "final_grads", "switch", "grads_per_chain", "n_unadj",
+                    "n_adj", "phase"):
+            assert a.get(key) == b.get(key), (key, a.get(key), b.get(key))
