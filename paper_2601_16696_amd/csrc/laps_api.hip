@@ -37,7 +37,6 @@ struct laps_ctx {
   void *u, *g, *sigma, *aux, *packed;
   double *logp, *delta, *acc, *partials, *shiftK, *mean, *var, *m2, *Vii, *ring, *wdelta, *part2;
   double *pS, *pW, *pPart;  // full-rank loss scratch
-  uint64_t *pZw;
   std::string err;
   // optional event pairs around the launches of one kernel (laps_kernel_log)
   int log_which = 0, log_every = 1;
@@ -199,7 +198,7 @@ struct Carve {
 
 struct Layout {
   size_t hyp, u, g, logp, delta, acc, partials, shiftK, mean, var, m2, Vii, ring, wdelta, part2, sigma, aux, packed,
-      pS, pW, pPart, pZw, total;
+      pS, pW, pPart, total;
 };
 
 int probe_chunks(int64_t N) { return (int)((N + kProbeChunk - 1) / kProbeChunk); }
@@ -246,7 +245,6 @@ Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
   L.pS = c.take((size_t)N * P * 8);
   L.pW = c.take((size_t)probe_chunks(N) * P * d * 8);
   L.pPart = c.take((size_t)(P > 0 ? probe_blocks(d, P) : 0) * 8);
-  L.pZw = c.take((size_t)P * ((d + 255) / 256) * 4 * 8);
   L.total = (size_t)round_up((int64_t)c.off, 256);
   return L;
 }
@@ -442,7 +440,6 @@ CtlArgs ctl_args(laps_ctx *c) {
   a.pS = c->pS;
   a.pW = c->pW;
   a.pPart = c->pPart;
-  a.pZw = c->pZw;
   return a;
 }
 
@@ -635,7 +632,6 @@ laps_status init_into(laps_ctx *c, const laps_config *cfg, const laps_target *tg
   c->pS = reinterpret_cast<double *>(w + L.pS);
   c->pW = reinterpret_cast<double *>(w + L.pW);
   c->pPart = reinterpret_cast<double *>(w + L.pPart);
-  c->pZw = reinterpret_cast<uint64_t *>(w + L.pZw);
   CtlArgs ca = ctl_args(c);
   hipError_t e;
   if ((e = hipMemsetAsync(c->shiftK, 0, (size_t)c->ld * 8, c->stream)) != hipSuccess ||

@@ -394,85 +394,116 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s) {
 // of this step and V_ij = -E[(x_i - xbar_i) g_j] from ensemble averages,
 //   D~ = (1/(P d)) sum_p |z_p + (1/N) sum_m (x_m - xbar)(g_m . z_p)|^2.
 // Probe entry i of z_p is 1 - 2b, b = bit i mod 64 of word (i mod 256) / 64 of
-// Philox block (p, i / 256, t, TAG_PROBE); only the probes' words are kept
-// (P ceil(d / 256) blocks per step), never the d x P probe matrix.
-// Four passes, every sum in a fixed order:
-//   k_probe_words:   the Philox words of every probe block, once per step
-//   k_probe_dots:    s[m][p] = g_m . z_p            (one thread per (m, p))
-//   k_probe_project: w_c[p][i] = sum over chunk c of (x_mi - xbar_i) s[m][p]
-//                    (chunks of 64 chains, so that d P NC threads share the work)
+// Philox block (p, i / 256, t, TAG_PROBE); probes are regenerated where they
+// are used (a lane computes the block of its own probe), never stored.
+// Three passes, every sum in a fixed order:
+//   k_probe_dots:    S = G Z, s[m][p] = g_m . z_p, on the FP64 matrix cores
+//                    (one wavefront per 16 chains x 16 probes, 4 dims per step)
+//   k_probe_project: W_c = S_c^T (X_c - xbar), w_c[p][i] = sum over chunk c of
+//                    (x_mi - xbar_i) s[m][p], on the FP64 matrix cores (one
+//                    wavefront per 16 probes x 16 dims of a kProbeChunk-chain
+//                    chunk)
 //   k_probe_norms:   per block, sum of (z_pi + (1/N) sum_c w_c[p][i])^2
-// and the controller adds the block sums in order.
+// and the controller adds the block sums in order.  Lane layout of
+// v_mfma_f64_16x16x4_f64 (A 16 x 4, B 4 x 16, D 16 x 16): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[l / 16 + 4 i][l % 16].
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_probe_words(CtlArgs c) {
-  const DevHyper *H = c.hyp;
-  if (H->phase != PH_UNADJ) return;
-  const int64_t nblk = (c.d + 255) / 256;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= c.probes * nblk) return;
-  const int64_t p = idx / nblk, blk = idx - p * nblk;
-  uint64_t w[4] = {(uint64_t)p, (uint64_t)blk, (uint64_t)H->t, (uint64_t)TAG_PROBE};
+typedef double pf64x4 __attribute__((ext_vector_type(4)));
+
+// The four Philox words of block blk (dims 256 blk .. 256 blk + 255) of probe p
+// at step t (all zero for a probe past the end), and entry i of that block.
+__device__ __forceinline__ void probe_words(const CtlArgs &c, int64_t p, int64_t blk, uint64_t t, uint64_t (&w)[4]) {
+  w[0] = (uint64_t)p;
+  w[1] = (uint64_t)blk;
+  w[2] = t;
+  w[3] = (uint64_t)TAG_PROBE;
   philox4x64_10(w, c.seed, 0);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) c.pZw[idx * 4 + k] = w[k];
+}
+__device__ __forceinline__ double probe_entry(const uint64_t (&w)[4], int64_t i) {
+  return ((w[(i & 255) >> 6] >> (i & 63)) & 1u) ? -1.0 : 1.0;
 }
 
 template <class Real>
 __global__ void __launch_bounds__(256) k_probe_dots(CtlArgs c) {
   const DevHyper *H = c.hyp;
   if (H->phase != PH_UNADJ) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t P = c.probes;
-  if (idx >= c.N * P) return;
-  const int64_t m = idx / P, p = idx - m * P;
-  const int64_t nblk = (c.d + 255) / 256;
-  const Real *g = static_cast<const Real *>(c.g) + m * c.ld;
-  double s = 0.0;
-  for (int64_t b0 = 0; b0 < c.d; b0 += 256) {
-    const uint64_t *zw = c.pZw + (p * nblk + b0 / 256) * 4;
-    const uint64_t w[4] = {zw[0], zw[1], zw[2], zw[3]};
-    const int64_t e = (c.d - b0 < 256) ? c.d - b0 : 256;
-    for (int64_t k = 0; k < e; k += 8) {
-      Real gv[8];
+  const int lane = threadIdx.x & 63;
+  const int64_t PT = (c.probes + 15) / 16;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ((c.N + 15) / 16) * PT) return;
+  const int64_t m0 = (tile / PT) * 16, p0 = (tile % PT) * 16;
+  const int lo = lane & 15, hi = lane >> 4;
+  const Real *g = static_cast<const Real *>(c.g);
+  const int64_t ma = m0 + lo, mc = ma < c.N ? ma : c.N - 1;  // A: g[ma][k0 + hi]
+  pf64x4 acc = pf64x4{0.0, 0.0, 0.0, 0.0};
+  const int64_t pb = p0 + lo;  // B: z[e][pb], from the words of the lane's own probe
+  uint64_t w[4] = {0, 0, 0, 0};
+  // 16 K-steps (64 dims) at a time: their operands are loaded before the first product
+  for (int64_t kb = 0; kb < c.d; kb += 64) {
+    if ((kb & 255) == 0) probe_words(c, pb, kb >> 8, (uint64_t)H->t, w);
+    // Indices are clamped to entries that exist and the bounds are applied as
+    // 0 / 1 factors, so that every load is used unconditionally: the compiler
+    // then issues all of them before the first wait instead of sinking each
+    // into a branch of its own that waits for it.
+    double av[16], bv[16];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) gv[j] = (k + j < e) ? g[b0 + k + j] : Real(0);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t b = k + j;
-        const double v = (double)gv[j];
-        s += ((w[b >> 6] >> (b & 63)) & 1u) ? -v : v;
-      }
+    for (int j = 0; j < 16; ++j) {
+      const int64_t e = kb + 4 * j + hi;
+      const double gv = (double)g[mc * c.ld + (e < c.d ? e : c.d - 1)];
+      av[j] = gv * ((ma < c.N && e < c.d) ? 1.0 : 0.0);
+      bv[j] = (pb < c.probes && e < c.d) ? probe_entry(w, e) : 0.0;
     }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], acc, 0, 0, 0);
   }
-  c.pS[m * P + p] = s;
+  const int64_t p = p0 + lo;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t m = m0 + hi + 4 * i;
+    if (m < c.N && p < c.probes) c.pS[m * c.probes + p] = acc[i];
+  }
 }
 
 template <class Real>
 __global__ void __launch_bounds__(256) k_probe_project(CtlArgs c) {
   const DevHyper *H = c.hyp;
   if (H->phase != PH_UNADJ) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int64_t P = c.probes, d = c.d;
-  if (idx >= d * P) return;
-  const int64_t p = idx / d, i = idx - p * d;
+  const int64_t PT = (P + 15) / 16, DTl = (d + 15) / 16;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= PT * DTl) return;
+  const int64_t p0 = (tile / DTl) * 16, i0 = (tile % DTl) * 16;
+  const int lo = lane & 15, hi = lane >> 4;
   const int64_t m0 = (int64_t)blockIdx.y * kProbeChunk;
   const int64_t m1 = (m0 + kProbeChunk < c.N) ? m0 + kProbeChunk : c.N;
   const Real *x = static_cast<const Real *>(c.x);
-  const double xb = c.mean[i];
-  double acc = 0.0;
-  int64_t m = m0;
-  for (; m + 4 <= m1; m += 4) {
-    double xv[4], sv[4];
+  const int64_t pa = p0 + lo, ib = i0 + lo;     // A: s[m][pa] (row pa, column m), B: x[m][ib] - xbar[ib]
+  const double xb = ib < d ? c.mean[ib] : 0.0;
+  pf64x4 acc = pf64x4{0.0, 0.0, 0.0, 0.0};
+  // the chunk's kProbeChunk / 4 K-steps: every operand is loaded before the first product
+  // (indices clamped and bounds applied as factors, as in k_probe_dots, so that
+  // all the loads are in flight together)
+  constexpr int KS = kProbeChunk / 4;
+  const int64_t pc = pa < P ? pa : P - 1, ic = ib < d ? ib : d - 1;
+  double av[KS], bv[KS];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      xv[j] = (double)x[(m + j) * c.ld + i];
-      sv[j] = c.pS[(m + j) * P + p];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc += (xv[j] - xb) * sv[j];
+  for (int j = 0; j < KS; ++j) {
+    const int64_t m = m0 + 4 * j + hi;
+    const bool ok = m < m1;
+    const int64_t mcl = ok ? m : m1 - 1;
+    const double sv = c.pS[mcl * P + pc];
+    const double xv = (double)x[mcl * c.ld + ic];
+    av[j] = sv * ((ok && pa < P) ? 1.0 : 0.0);
+    bv[j] = (xv - xb) * ((ok && ib < d) ? 1.0 : 0.0);
   }
-  for (; m < m1; ++m) acc += ((double)x[m * c.ld + i] - xb) * c.pS[m * P + p];
-  c.pW[((int64_t)blockIdx.y * P + p) * d + i] = acc;
+#pragma unroll
+  for (int j = 0; j < KS; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], acc, 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t pp = p0 + hi + 4 * i;
+    if (pp < P && ib < d) c.pW[((int64_t)blockIdx.y * P + pp) * d + ib] = acc[i];
+  }
 }
 
 __global__ void __launch_bounds__(256) k_probe_norms(CtlArgs c) {
@@ -485,9 +516,11 @@ __global__ void __launch_bounds__(256) k_probe_norms(CtlArgs c) {
   if (idx < d * P) {
     const int64_t p = idx / d, i = idx - p * d;
     double w = 0.0;
+#pragma unroll 8
     for (int ch = 0; ch < c.NC; ++ch) w += c.pW[((int64_t)ch * P + p) * d + i];
-    const uint64_t word = c.pZw[(p * ((d + 255) / 256) + i / 256) * 4 + ((i & 255) >> 6)];
-    const double z = ((word >> (i & 63)) & 1u) ? -1.0 : 1.0;
+    uint64_t wz[4];
+    probe_words(c, p, i >> 8, (uint64_t)H->t, wz);
+    const double z = probe_entry(wz, i);
     const double r = z + w / (double)c.N;
     v = r * r;
   }
@@ -499,9 +532,9 @@ __global__ void __launch_bounds__(256) k_probe_norms(CtlArgs c) {
 
 hipError_t launch_probes(const CtlArgs &c, hipStream_t s) {
   if (c.probes <= 0) return hipSuccess;
-  const int64_t nd = c.N * c.probes, dp = c.d * c.probes, nw = c.probes * ((c.d + 255) / 256);
-  const dim3 g1((unsigned)((nd + 255) / 256)), g2((unsigned)((dp + 255) / 256), (unsigned)c.NC);
-  hipLaunchKernelGGL(k_probe_words, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, c);
+  const int64_t PT = (c.probes + 15) / 16;
+  const int64_t t1 = ((c.N + 15) / 16) * PT, t2 = PT * ((c.d + 15) / 16);  // 16 x 16 tiles, one per wavefront
+  const dim3 g1((unsigned)((t1 + 3) / 4)), g2((unsigned)((t2 + 3) / 4), (unsigned)c.NC);
   if (c.sigma_double) {
     hipLaunchKernelGGL(k_probe_dots<double>, g1, dim3(256), 0, s, c);
     hipLaunchKernelGGL(k_probe_project<double>, g2, dim3(256), 0, s, c);

@@ -62,14 +62,13 @@ struct CtlArgs {
   uint64_t seed;
   const void *x, *g;
   double *pS, *pW, *pPart;
-  uint64_t *pZw;           // the probes' Philox words of this step [P][ceil(d / 256)][4]
 };
 
 enum { FIN_INIT = 0, FIN_UNADJ = 1 };
 // dimensions per workgroup of the statistics pass (its block count is
 // ceil(d / fin_dims(d)))
 __host__ __device__ inline int fin_dims(int64_t d) { return d <= 1024 ? 8 : 32; }
-constexpr int kProbeChunk = 64;  // chains per partial projection of the full-rank loss
+constexpr int kProbeChunk = 128;  // chains per partial projection of the full-rank loss
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_hyper_init(const CtlArgs &c, hipStream_t s);
