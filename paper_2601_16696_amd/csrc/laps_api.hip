@@ -37,6 +37,9 @@ struct laps_ctx {
   void *u, *g, *sigma, *aux, *packed;
   double *logp, *delta, *acc, *partials, *shiftK, *mean, *var, *m2, *Vii, *ring, *wdelta, *part2;
   double *pS, *pW, *pPart;  // full-rank loss scratch
+  void *zn;                 // normals of the next unadjusted step (zn_blocks > 0)
+  uint64_t *zn_tag;
+  int zn_blocks;
   std::string err;
   // optional event pairs around the launches of one kernel (laps_kernel_log)
   int log_which = 0, log_every = 1;
@@ -198,8 +201,21 @@ struct Carve {
 
 struct Layout {
   size_t hyp, u, g, logp, delta, acc, partials, shiftK, mean, var, m2, Vii, ring, wdelta, part2, sigma, aux, packed,
-      pS, pW, pPart, total;
+      pS, pW, pPart, zn, zn_tag, total;
 };
+
+// Workgroups appended to an unadjusted-step launch to compute the next step's
+// normals ahead (0: none).  FP64 state of the per-chain targets only (FP32
+// normals use the hardware transcendentals and cost little), and only when
+// the chain workgroups occupy at most half of the 1024 SIMDs, so that the
+// appended ones run on compute units that would otherwise idle.
+int noise_blocks(const laps_config *cfg, const laps_target *tg, const Shape &s) {
+  if (!is_local(tg->kind) || cfg->prec != LAPS_F64) return 0;
+  const int64_t grid = s.split ? s.grid_full : s.G;
+  if (grid * ((s.block + 63) / 64) > 512) return 0;
+  const int64_t items = 2 * cfg->n_chains * ((cfg->d + 7) / 8);  // one thread per oct and refresh
+  return (int)((items + s.block - 1) / s.block);
+}
 
 int probe_chunks(int64_t N) { return (int)((N + kProbeChunk - 1) / kProbeChunk); }
 int probe_blocks(int64_t d, int64_t P) { return (int)((d * P + 255) / 256); }
@@ -245,6 +261,9 @@ Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
   L.pS = c.take((size_t)N * P * 8);
   L.pW = c.take((size_t)probe_chunks(N) * P * d * 8);
   L.pPart = c.take((size_t)(P > 0 ? probe_blocks(d, P) : 0) * 8);
+  const bool zn = noise_blocks(cfg, tg, s) > 0;
+  L.zn = c.take(zn ? (size_t)4 * N * ld * rs : 0);
+  L.zn_tag = c.take(zn ? 2 * sizeof(uint64_t) : 0);
   L.total = (size_t)round_up((int64_t)c.off, 256);
   return L;
 }
@@ -476,7 +495,13 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     a.stats = (phase_stats && !c->split) ? 1 : 0;
     // the full-rank loss reads the step's gradients, so they are kept
     a.cache = (phase_stats && (c->split || (kk == KK_UNADJ && c->cfg.full_rank_probes > 0))) ? 1 : 0;
-    const int grid = (phase_stats && !c->split) ? c->G : c->grid_full;
+    int grid = (phase_stats && !c->split) ? c->G : c->grid_full;
+    if (kk == KK_UNADJ && c->zn_blocks > 0) {
+      a.zn = c->zn;
+      a.zn_tag = c->zn_tag;
+      a.zn_blocks = c->zn_blocks;
+      grid += c->zn_blocks;
+    }
     const bool mams = kk == KK_MAMS_MN2 || kk == KK_MAMS_MN4;
     const int which = kk == KK_UNADJ ? LAPS_KERNEL_UNADJ : (mams ? LAPS_KERNEL_MAMS : 0);
     hipError_t e = logged(c, which, [&] {
@@ -632,11 +657,15 @@ laps_status init_into(laps_ctx *c, const laps_config *cfg, const laps_target *tg
   c->pS = reinterpret_cast<double *>(w + L.pS);
   c->pW = reinterpret_cast<double *>(w + L.pW);
   c->pPart = reinterpret_cast<double *>(w + L.pPart);
+  c->zn_blocks = noise_blocks(cfg, tg, s);
+  c->zn = c->zn_blocks > 0 ? w + L.zn : nullptr;
+  c->zn_tag = c->zn_blocks > 0 ? reinterpret_cast<uint64_t *>(w + L.zn_tag) : nullptr;
   CtlArgs ca = ctl_args(c);
   hipError_t e;
   if ((e = hipMemsetAsync(c->shiftK, 0, (size_t)c->ld * 8, c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(c->u, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess ||
-      (e = hipMemsetAsync(c->g, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess)
+      (e = hipMemsetAsync(c->g, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess ||
+      (c->zn_tag && (e = hipMemsetAsync(c->zn_tag, 0, 2 * sizeof(uint64_t), c->stream)) != hipSuccess))
     return fail(c, e, "workspace clear");
   if (tg->kind == LAPS_GAUSS_DIAG || tg->kind == LAPS_STOCHVOL)
     e = launch_prep_aux(tg->kind, c->dbl, tg->data[0], c->aux, cfg->d, c->ld, c->stream);
@@ -1052,7 +1081,13 @@ extern "C" laps_status laps_time_kernel(laps_ctx *c, int32_t which, int32_t n_re
   LocalArgs a = local_args(c);
   a.stats = 0;
   a.cache = c->split ? 1 : 0;
-  const int grid = c->grid_full;
+  int grid = c->grid_full;
+  if (kk == KK_UNADJ && c->zn_blocks > 0) {
+    a.zn = c->zn;
+    a.zn_tag = c->zn_tag;
+    a.zn_blocks = c->zn_blocks;
+    grid += c->zn_blocks;
+  }
   hipError_t e = hipEventRecord(e0, c->stream);
   for (int32_t k = 0; k < n_reps && e == hipSuccess; ++k)
     e = launch_local(c->tg.kind, c->dbl, c->Q, kk, a, grid, c->block, which == 1 ? c->shmem : c->shmem_sig,

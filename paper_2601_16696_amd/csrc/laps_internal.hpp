@@ -35,6 +35,12 @@ struct LocalArgs {
   int stats;               // accumulate per-dim sums in the step kernel (1) or leave them to k_stats (0)
   double *logp_out;        // target eval: log p output
   void *g_out;             // target eval: gradient output (or null)
+  // unadjusted step: normals written one step ahead by zn_blocks workgroups
+  // appended to the launch, [2 slots][2 refreshes][N][ld] of the state type;
+  // slot t % 2 holds step t's normals when zn_tag[t % 2] == t + 1
+  void *zn;
+  uint64_t *zn_tag;
+  int zn_blocks;
 };
 
 // Arguments of the statistics / controller kernels.

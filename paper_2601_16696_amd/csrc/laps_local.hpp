@@ -482,13 +482,60 @@ __global__ void __launch_bounds__(512) k_init(LocalArgs a) {
 // Ensemble sums of the new state go to the workgroup's partial row (STATS) or
 // are left to the column-sum kernel, which reads the stored x and g.
 // ---------------------------------------------------------------------------
+//
+// When the chain workgroups leave compute units idle (few chains, FP64
+// normals), zn_blocks more workgroups are appended to the launch.  They
+// compute the normals of the two partial refreshes of step t + 1 (one Philox
+// block and four Box-Muller pairs per thread and oct, the values oct_normals
+// returns) into the slot of step t + 1 and tag it; the next step's chain
+// workgroups then load their normals instead of computing them, and compute
+// them as before when the slot is not tagged with their step.  The normals
+// depend only on (seed, chain, oct, step), so a tagged slot is valid across
+// restarts, and a step's results do not depend on where its normals came from.
+template <class Real>
+__device__ void fill_step_noise(const LocalArgs &a, uint64_t t1, int64_t idx) {
+  const int64_t octs = (a.d + 7) / 8, per = a.N * octs;
+  if (idx == 0) a.zn_tag[t1 & 1] = t1 + 1;
+  if (idx >= 2 * per) return;
+  const int k = (int)(idx / per);
+  const int64_t rem = idx - k * per, m = rem / octs, oct = rem - m * octs;
+  Real z[8];
+  oct_normals<Real>(a.seed, (uint64_t)m, oct, a.d, t1, k == 0 ? TAG_O_FIRST : TAG_O_SECOND, 0, z);
+  st8<Real>(static_cast<Real *>(a.zn) + (((int64_t)(t1 & 1) * 2 + k) * a.N + m) * a.ld + 8 * oct, z);
+}
+
+// The normals of refresh k (0 first, 1 second) of step t for oct `oct` of
+// chain m: from the tagged slot zs when there is one, else computed.
+template <class Real>
+__device__ __forceinline__ void step_normals(const LocalArgs &a, const Real *zs, bool act, int k, int64_t m,
+                                             int64_t oct, uint64_t t, Real (&z)[8]) {
+  if (zs) {
+    if (act && 8 * oct < a.d) {
+      ld8<Real>(zs + ((int64_t)k * a.N + m) * a.ld + 8 * oct, z);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) z[i] = Real(0);
+    }
+  } else {
+    oct_normals<Real>(a.seed, (uint64_t)m, oct, a.d, t, k == 0 ? TAG_O_FIRST : TAG_O_SECOND, 0, z);
+  }
+}
+
 template <class Real, int Q, class Tgt, bool STATS>
 __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
   const DevHyper *H = a.hyp;
   if (H->phase != PH_UNADJ) return;
+  const int cgrid = (int)gridDim.x - a.zn_blocks;  // chain workgroups
+  if ((int)blockIdx.x >= cgrid) {
+    fill_step_noise<Real>(a, (uint64_t)H->t + 1, (int64_t)(blockIdx.x - cgrid) * blockDim.x + threadIdx.x);
+    return;
+  }
   LAPS_TEAM_PROLOGUE(false)
   const double eps = H->eps, Lm = H->L;
   const uint64_t t = (uint64_t)H->t;
+  const Real *zs = (a.zn_blocks > 0 && a.zn_tag[t & 1] == t + 1)
+                       ? static_cast<const Real *>(a.zn) + (size_t)(t & 1) * 2 * N * ld
+                       : nullptr;
   const double h = 0.5 * eps;
   const double c1d = exp(-h / Lm), c2d = sqrt(-expm1(-2.0 * h / Lm)) / sqrt((double)d);
   const Real c1 = (Real)c1d, c2 = (Real)c2d, epsR = (Real)eps;
@@ -500,7 +547,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
   Real *X = static_cast<Real *>(a.x);
   Real *U = static_cast<Real *>(a.u);
   Real *Gb = static_cast<Real *>(a.g);
-  for (int64_t base = (int64_t)blockIdx.x * a.tpw; base < N; base += (int64_t)gridDim.x * a.tpw) {
+  for (int64_t base = (int64_t)blockIdx.x * a.tpw; base < N; base += (int64_t)cgrid * a.tpw) {
     const int64_t m = base + team;
     const bool act = m < N;
     Real x[Q][8], u[Q][8], g[Q][8];
@@ -518,7 +565,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       Real z[8];
-      oct_normals<Real>(a.seed, (uint64_t)m, r + q * T, d, t, TAG_O_FIRST, 0, z);
+      step_normals<Real>(a, zs, act, 0, m, r + q * T, t, z);
       Real p1 = Real(0), p2 = Real(0), p3 = Real(0);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
@@ -564,7 +611,7 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       Real z[8];
-      oct_normals<Real>(a.seed, (uint64_t)m, r + q * T, d, t, TAG_O_SECOND, 0, z);
+      step_normals<Real>(a, zs, act, 1, m, r + q * T, t, z);
       Real p1 = Real(0);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
