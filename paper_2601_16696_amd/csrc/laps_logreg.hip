@@ -474,26 +474,38 @@ __global__ void __launch_bounds__(256) k_lr_grad_f64_mfma(LogregArgs a) {
   int64_t r1 = r0 + (int64_t)a.bps * 32;
   if (r1 > n) r1 = n;
   const int64_t ntile = (r1 - r0 + 15) / 16;
-  // staging of row tile tt into buffer b: 16 rows x ld doubles (zero past d and n), and the labels
+  // staging of row tile tt into buffer b: 16 rows x ld doubles (zero past d and n), and the labels.
+  // Thread tid copies row tid / 16, columns tid % 16 + 16 j; the loads use clamped in-range indices
+  // and the bounds enter as 0 / 1 factors (X is finite), so none of them waits in a branch of its own.
   auto stage = [&](int64_t tt, int b) {
     const int64_t rb = r0 + 16 * tt;
-    for (int i = tid; i < 16 * (int)ld; i += 256) {
-      const int rr = i / (int)ld, e = i - rr * (int)ld;
-      const int64_t row = rb + rr;
-      Xs[(b * 16 + rr) * ldl + e] = (row < r1 && e < d) ? X[row * d + e] : 0.0;
-    }
+    const int rr = tid >> 4;
+    const int64_t row = rb + rr;
+    const double rf = row < r1 ? 1.0 : 0.0;
+    const double *src = X + (row < r1 ? row : r1 - 1) * d;
+    double *dst = Xs + (b * 16 + rr) * ldl;
+    for (int e = tid & 15; e < (int)ld; e += 16) dst[e] = src[e < d ? e : d - 1] * (e < d ? rf : 0.0);
     if (tid < 16) Ys[b * 16 + tid] = (rb + tid < r1) ? a.y[rb + tid] : 0.0;
   };
   if (ntile > 0) stage(0, 0);
   __syncthreads();
+  // softplus(z) = max(z, 0) + log(1 + e^{-|z|}): the factors 1 + e^{-|z|} in (1, 2] of the lane's rows
+  // are multiplied and their logarithm taken once per 8 tiles (32 factors, below 2^32); rounding each
+  // factor to FP64 costs at most 2^-53 absolute in its logarithm
+  double pf = 1.0;
   for (int64_t tt = 0; tt < ntile; ++tt) {
     const int b = (int)(tt & 1);
     if (tt + 1 < ntile) stage(tt + 1, b ^ 1);
     const double *T = Xs + b * 16 * ldl;
-    // forward: A = X[row lo][4 k + hi]
-    f64x4 z = f64x4{0.0, 0.0, 0.0, 0.0};
+    // forward: A = X[row lo][4 k + hi], even and odd K-steps in two accumulators (two dependency chains)
+    f64x4 z0 = f64x4{0.0, 0.0, 0.0, 0.0}, z1 = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < KS; ++k) z = __builtin_amdgcn_mfma_f64_16x16x4f64(T[lo * ldl + 4 * k + hi], th[k], z, 0, 0, 0);
+    for (int k = 0; k < KS; k += 2) {
+      z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(T[lo * ldl + 4 * k + hi], th[k], z0, 0, 0, 0);
+      if (k + 1 < KS)
+        z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(T[lo * ldl + 4 * (k + 1) + hi], th[k + 1], z1, 0, 0, 0);
+    }
+    const f64x4 z = z0 + z1;
     // epilogue on the lane's rows hi + 4 i of chain m
     const int64_t rb = r0 + 16 * tt;
     double rv[4];
@@ -503,10 +515,16 @@ __global__ void __launch_bounds__(256) k_lr_grad_f64_mfma(LogregArgs a) {
       const double zz = z[i];
       const double yv = Ys[b * 16 + rr];
       const double ez = exp(-fabs(zz));
-      const double sg = (zz >= 0.0 ? 1.0 : ez) / (1.0 + ez);
+      const double q = 1.0 + ez;
+      const double sg = (zz >= 0.0 ? 1.0 : ez) / q;
       const bool ok = rb + rr < r1;
       rv[i] = ok ? yv - sg : 0.0;
-      lacc += ok ? yv * zz - (fmax(zz, 0.0) + log1p(ez)) : 0.0;
+      lacc += ok ? yv * zz - fmax(zz, 0.0) : 0.0;
+      pf *= ok ? q : 1.0;
+    }
+    if ((tt & 7) == 7) {
+      lacc -= log(pf);
+      pf = 1.0;
     }
     // backward: K-step i takes the rows hi + 4 i (A = r from registers, B = X[row][16 t + lo])
 #pragma unroll
@@ -532,6 +550,7 @@ __global__ void __launch_bounds__(256) k_lr_grad_f64_mfma(LogregArgs a) {
       if (mc < N && e < ld) Gp[((int64_t)s * N + mc) * ld + e] = gacc[t][i];
     }
   }
+  lacc -= log(pf);
   // log p partial of chain m: the lanes with equal lo hold its rows (xor over hi)
   lacc += __shfl_xor(lacc, 16);
   lacc += __shfl_xor(lacc, 32);
