@@ -5,7 +5,9 @@ workload), against the oracle:
 - diagonal Gaussian and rotated ill-conditioned Gaussian (dense gradient),
   d = 100, 1024 chains, FP64: 100 unadjusted steps (eps, L, D~ within 1e-9
   at every step, every chain's position within 1e-10 after 100 steps, 1e-9
-  for the condition-1e5 target), then MAMS transitions;
+  for the condition-1e5 target), then MAMS transitions; and the same 100
+  steps with the controllers free throughout (eps within 2e-7, positions
+  within 1e-7);
 - stochastic volatility, T = 2427, 4096 chains, and phi^4, 64 x 64, 2048
   chains, FP32 state: 10 unadjusted steps for every chain with the oracle
   replaying the GPU's (eps, L), positions within 1e-4;
@@ -95,6 +97,40 @@ def test_fp64_full_size(gpu, orc, name, n_unadj, n_adj, xtol):
         assert _close(sg["eps"], so["eps"], 1e-9), (k, sg["eps"], so["eps"])
     err = _rel_rows(s.positions().cpu().numpy(), o.array("x"))
     assert np.max(err) < xtol, np.max(err)
+
+
+# Free-running bounds over 100 steps, about 4x the largest differences measured
+# on the MI355X (eps 5.0e-8, D~ 1.7e-8, EEVPD 3.2e-7 relative, for the
+# ill-conditioned target; positions 1.4e-8 for the diagonal one)
+FREE_TOL = dict(eps=2e-7, L=1e-8, dtilde=1e-7, eevpd=2e-6)
+FREE_XTOL = 1e-7
+
+
+@pytest.mark.parametrize("name", ["gauss", "ill_gauss"])
+def test_fp64_full_size_free_controller(gpu, orc, name):
+    """100 unadjusted steps with both controllers free throughout (no
+    replay).  The step size is fed back from the ensemble's energy-error
+    variance (section "Unadjusted initialization", "Step size"), so
+    differences in the last digit of the per-chain energy errors (the two
+    sides sum in different orders) reach eps and through it the positions.
+    They stay bounded, not growing step over step: the controller damps them
+    (measured: at most 5e-8 in eps and 1.4e-8 in any chain's position after
+    100 steps)."""
+    w = workloads.gaussian() if name == "gauss" else workloads.ill_gaussian()
+    o, s = _pair(gpu, orc, w, "f64", switch_policy=1, max_steps_unadj=100, max_steps_total=100 + 15 * 3)
+    worst = dict.fromkeys(FREE_TOL, 0.0)
+    for k in range(100):
+        o.step_unadjusted(1)
+        s.step_unadjusted(1)
+        so, sg = o.stats(), s.stats()
+        assert sg["t"] == so["t"] and sg["phase"] == so["phase"]
+        for key, tol in FREE_TOL.items():
+            rel = abs(sg[key] - so[key]) / max(abs(so[key]), 1e-300)
+            worst[key] = max(worst[key], rel)
+            assert rel <= tol, (k, key, sg[key], so[key])
+    err = _rel_rows(s.positions().cpu().numpy(), o.array("x"))
+    print(name, "largest relative differences over 100 free steps:", worst, "positions:", np.max(err))
+    assert np.max(err) < FREE_XTOL, np.max(err)
 
 
 @pytest.mark.parametrize("name", ["stochvol", "phi4"])
