@@ -9,10 +9,11 @@
  * where it is taken.
  *
  * Parity status: every function here is pinned by a CPU test against a
- * closed form, a library routine, an invariant or brute force, except the
+ * closed form, a library routine, an invariant or brute force.  The
  * unadjusted controller trajectory as a whole (the eps(t) schedule and the
- * switch time), which has no closed form: parity unpinned beyond the
- * arithmetic checks of its single update.
+ * switch time) has no closed form: it is pinned by its single update's
+ * arithmetic and by its equivariance under a change of units, and is
+ * otherwise parity unpinned.
  */
 #include "laps_oracle.h"
 

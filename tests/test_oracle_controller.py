@@ -299,3 +299,49 @@ def test_fixed_step_size_at_eps0_matches_the_first_adaptive_step(orc):
 def test_fixed_step_size_rejects_negative(orc):
     with pytest.raises(ValueError):
         orc.Ensemble(orc.Target(orc.GAUSS_DIAG, 3, a=np.ones(3)), 4, 1, eps_fixed=-1.0)
+
+
+@pytest.mark.parametrize("f", [2.0, 0.5])
+def test_unadjusted_trajectory_is_scale_equivariant(orc, f):
+    """The unadjusted controller's whole trajectory under a change of units.
+    Scaling a diagonal Gaussian's standard deviations, the start and the
+    initial step size by f leaves every quantity the controller reads
+    unchanged: the energy errors (eq. (discrete update): eps |g| and h / L
+    are unit-free), D~ (V_ii = -E[(x_i - xbar_i) d_i log p]), EEVPD and the
+    moving window's relative fluctuations of E[x_i^2] (section "Switch to
+    adjustment"); it scales eps and L = alpha (sum Var)^{1/2} by f and
+    sum Var by f^2.  With f a power of two every FP64 operation scales
+    exactly, so the eps(t), L(t) schedule, the window switch's step and the
+    final positions must be the unscaled run's times f bit for bit.  A slip
+    in the units of a controller formula (L without its square root, a drift
+    not multiplied by eps, a window spread not divided by its mean) breaks
+    this; a wrong exponent inside a unit-free ratio does not, and is pinned
+    by the single-update tests above."""
+    d, N = 20, 512
+    rng = np.random.default_rng(7)
+    s2 = 10.0 ** rng.uniform(-1, 1, size=d)
+    x0 = rng.normal(size=(N, d)) * 3.0
+    cfg = dict(switch_policy=0, switch_tol=0.1, max_steps_unadj=600, max_steps_total=720)
+    runs = []
+    for sc in (1.0, f):
+        e = orc.Ensemble(orc.Target(orc.GAUSS_DIAG, d, a=s2 * sc * sc), N, 11, eps0_factor=0.01 * sc, **cfg)
+        e.init(x0 * sc)
+        hist = [e.stats()]
+        while hist[-1]["phase"] == 0:
+            e.step_unadjusted(1)
+            hist.append(e.stats())
+        runs.append((hist, e.array("x"), e.array("delta")))
+    (h1, x1, D1), (hf, xf, Df) = runs
+    assert len(h1) == len(hf)
+    last = h1[-1]
+    # the switch came from the window criterion, not from the step limit
+    assert last["switch_ready"] == 1 and 20 < last["t"] < cfg["max_steps_unadj"], last
+    same = ("t", "phase", "switch_ready", "status_bits", "n_nonfinite", "ring_full", "dtilde", "eevpd",
+            "eevpd_target", "max_delta")
+    for a, b in zip(h1, hf):
+        for key in same:
+            assert a[key] == b[key] or (a[key] != a[key] and b[key] != b[key]), (a["t"], key, a[key], b[key])
+        assert b["eps"] == f * a["eps"] and b["L"] == f * a["L"], (a["t"], a["eps"], b["eps"], a["L"], b["L"])
+        assert b["sum_var"] == f * f * a["sum_var"], (a["t"], a["sum_var"], b["sum_var"])
+    np.testing.assert_array_equal(xf, f * x1)
+    np.testing.assert_array_equal(Df, D1)
