@@ -62,8 +62,8 @@ SIMDS, CLOCK_HZ = 1024, 2.4e9  # 256 CUs x 4 SIMDs at 2.4 GHz
 # Vector instructions (SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32) per launch of the per-chain step kernels,
 # from the counter summary under profiles/; reset to None whenever a kernel changes.
 STEP_INSTS = {
-    "stochvol": {"unadj": (32497665, 913409), "mams": (942860609, 27885571)},
-    "phi4": {"unadj": (22034432, 577536), "mams": (552040953, 9981952)},
+    "stochvol": {"unadj": (30375937, 909313), "mams": (942860609, 27885571)},
+    "phi4": {"unadj": (20598784, 571392), "mams": (552040953, 9981952)},
 }
 
 

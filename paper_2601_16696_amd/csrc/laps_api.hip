@@ -487,6 +487,19 @@ hipError_t logged(laps_ctx *c, int which, F &&launch) {
   return e;
 }
 
+// Workgroups of an unadjusted-step launch.  The split-statistics path (teams
+// wider than a wavefront or several octs per lane, as at C3 and C4) runs every
+// chain in one round when the full grid holds at least 4 wavefronts per SIMD,
+// and then all wavefronts load, compute and store in step; with half the grid
+// each team steps two chains in turn and the wavefronts drift apart, so one
+// loads while another computes (measured: SV T = 2427 step 143.5 -> 136.8 us,
+// phi^4 64 x 64 86.5 -> 79.5 us; a quarter of the grid was slower).
+int unadj_grid(const laps_ctx *c) {
+  if (!c->split) return c->G;
+  const int64_t waves = (int64_t)c->grid_full * ((c->block + 63) / 64);
+  return waves >= 4 * 1024 ? (c->grid_full + 1) / 2 : c->grid_full;
+}
+
 laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
   if (is_local(c->tg.kind)) {
     LocalArgs a = local_args(c);
@@ -495,7 +508,7 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
     a.stats = (phase_stats && !c->split) ? 1 : 0;
     // the full-rank loss reads the step's gradients, so they are kept
     a.cache = (phase_stats && (c->split || (kk == KK_UNADJ && c->cfg.full_rank_probes > 0))) ? 1 : 0;
-    int grid = (phase_stats && !c->split) ? c->G : c->grid_full;
+    int grid = kk == KK_UNADJ ? unadj_grid(c) : ((phase_stats && !c->split) ? c->G : c->grid_full);
     if (kk == KK_UNADJ && c->zn_blocks > 0) {
       a.zn = c->zn;
       a.zn_tag = c->zn_tag;
@@ -1081,7 +1094,7 @@ extern "C" laps_status laps_time_kernel(laps_ctx *c, int32_t which, int32_t n_re
   LocalArgs a = local_args(c);
   a.stats = 0;
   a.cache = c->split ? 1 : 0;
-  int grid = c->grid_full;
+  int grid = (kk == KK_UNADJ && c->split) ? unadj_grid(c) : c->grid_full;
   if (kk == KK_UNADJ && c->zn_blocks > 0) {
     a.zn = c->zn;
     a.zn_tag = c->zn_tag;
