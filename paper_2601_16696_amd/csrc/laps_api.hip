@@ -40,6 +40,9 @@ struct laps_ctx {
   void *zn;                 // normals of the next unadjusted step (zn_blocks > 0)
   uint64_t *zn_tag;
   int zn_blocks;
+  void *zm;                 // normals of the next MAMS transition (zm_blocks > 0)
+  uint64_t *zm_tag;
+  int zm_blocks;
   std::string err;
   // optional event pairs around the launches of one kernel (laps_kernel_log)
   int log_which = 0, log_every = 1;
@@ -201,7 +204,7 @@ struct Carve {
 
 struct Layout {
   size_t hyp, u, g, logp, delta, acc, partials, shiftK, mean, var, m2, Vii, ring, wdelta, part2, sigma, aux, packed,
-      pS, pW, pPart, zn, zn_tag, total;
+      pS, pW, pPart, zn, zn_tag, zm, zm_tag, total;
 };
 
 // Workgroups appended to an unadjusted-step launch to compute the next step's
@@ -215,6 +218,18 @@ int noise_blocks(const laps_config *cfg, const laps_target *tg, const Shape &s) 
   if (grid * ((s.block + 63) / 64) > 512) return 0;
   const int64_t items = 2 * cfg->n_chains * ((cfg->d + 7) / 8);  // one thread per oct and refresh
   return (int)((items + s.block - 1) / s.block);
+}
+
+// Workgroups appended to a MAMS launch to compute the next transition's
+// normals (0: none): on the same shapes as noise_blocks with one oct per lane
+// (the kernel holds the next step's normals across the gradient stages only
+// then), about 8 normals blocks per thread so that they finish well within
+// the transition, and at most 512 workgroups in all.
+int mams_noise_blocks(const laps_config *cfg, const laps_target *tg, const Shape &s) {
+  if (noise_blocks(cfg, tg, s) == 0 || s.Q != 1 || cfg->n_steps_traj < 1) return 0;
+  const int64_t items = (2 * (int64_t)cfg->n_steps_traj + 1) * cfg->n_chains * ((cfg->d + 7) / 8);
+  const int64_t nb = (items + 8 * (int64_t)s.block - 1) / (8 * (int64_t)s.block);
+  return s.grid_full + nb <= 512 ? (int)nb : 0;
 }
 
 int probe_chunks(int64_t N) { return (int)((N + kProbeChunk - 1) / kProbeChunk); }
@@ -264,6 +279,9 @@ Layout layout(const laps_config *cfg, const laps_target *tg, const Shape &s) {
   const bool zn = noise_blocks(cfg, tg, s) > 0;
   L.zn = c.take(zn ? (size_t)4 * N * ld * rs : 0);
   L.zn_tag = c.take(zn ? 2 * sizeof(uint64_t) : 0);
+  const bool zm = mams_noise_blocks(cfg, tg, s) > 0;
+  L.zm = c.take(zm ? (size_t)2 * (2 * cfg->n_steps_traj + 1) * N * ld * rs : 0);
+  L.zm_tag = c.take(zm ? 2 * sizeof(uint64_t) : 0);
   L.total = (size_t)round_up((int64_t)c.off, 256);
   return L;
 }
@@ -516,6 +534,12 @@ laps_status enqueue_chain_kernel(laps_ctx *c, KernelKind kk, const void *u0) {
       grid += c->zn_blocks;
     }
     const bool mams = kk == KK_MAMS_MN2 || kk == KK_MAMS_MN4;
+    if (mams && c->zm_blocks > 0) {
+      a.zm = c->zm;
+      a.zm_tag = c->zm_tag;
+      a.zm_blocks = c->zm_blocks;
+      grid += c->zm_blocks;
+    }
     const int which = kk == KK_UNADJ ? LAPS_KERNEL_UNADJ : (mams ? LAPS_KERNEL_MAMS : 0);
     hipError_t e = logged(c, which, [&] {
       return launch_local(c->tg.kind, c->dbl, c->Q, kk, a, grid, c->block, mams ? c->shmem_sig : c->shmem,
@@ -673,12 +697,16 @@ laps_status init_into(laps_ctx *c, const laps_config *cfg, const laps_target *tg
   c->zn_blocks = noise_blocks(cfg, tg, s);
   c->zn = c->zn_blocks > 0 ? w + L.zn : nullptr;
   c->zn_tag = c->zn_blocks > 0 ? reinterpret_cast<uint64_t *>(w + L.zn_tag) : nullptr;
+  c->zm_blocks = mams_noise_blocks(cfg, tg, s);
+  c->zm = c->zm_blocks > 0 ? w + L.zm : nullptr;
+  c->zm_tag = c->zm_blocks > 0 ? reinterpret_cast<uint64_t *>(w + L.zm_tag) : nullptr;
   CtlArgs ca = ctl_args(c);
   hipError_t e;
   if ((e = hipMemsetAsync(c->shiftK, 0, (size_t)c->ld * 8, c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(c->u, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess ||
       (e = hipMemsetAsync(c->g, 0, (size_t)cfg->n_chains * c->ld * (c->dbl ? 8 : 4), c->stream)) != hipSuccess ||
-      (c->zn_tag && (e = hipMemsetAsync(c->zn_tag, 0, 2 * sizeof(uint64_t), c->stream)) != hipSuccess))
+      (c->zn_tag && (e = hipMemsetAsync(c->zn_tag, 0, 2 * sizeof(uint64_t), c->stream)) != hipSuccess) ||
+      (c->zm_tag && (e = hipMemsetAsync(c->zm_tag, 0, 2 * sizeof(uint64_t), c->stream)) != hipSuccess))
     return fail(c, e, "workspace clear");
   if (tg->kind == LAPS_GAUSS_DIAG || tg->kind == LAPS_STOCHVOL)
     e = launch_prep_aux(tg->kind, c->dbl, tg->data[0], c->aux, cfg->d, c->ld, c->stream);
@@ -1100,6 +1128,12 @@ extern "C" laps_status laps_time_kernel(laps_ctx *c, int32_t which, int32_t n_re
     a.zn_tag = c->zn_tag;
     a.zn_blocks = c->zn_blocks;
     grid += c->zn_blocks;
+  }
+  if (kk != KK_UNADJ && c->zm_blocks > 0) {
+    a.zm = c->zm;
+    a.zm_tag = c->zm_tag;
+    a.zm_blocks = c->zm_blocks;
+    grid += c->zm_blocks;
   }
   hipError_t e = hipEventRecord(e0, c->stream);
   for (int32_t k = 0; k < n_reps && e == hipSuccess; ++k)

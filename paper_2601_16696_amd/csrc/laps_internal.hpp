@@ -41,6 +41,12 @@ struct LocalArgs {
   void *zn;
   uint64_t *zn_tag;
   int zn_blocks;
+  // MAMS transition: the next transition's normals written by zm_blocks
+  // appended workgroups, [2 slots][2 n_traj + 1][N][ld]; slot (t / n_traj) % 2
+  // holds the transition starting at t when zm_tag[slot] == t + 1
+  void *zm;
+  uint64_t *zm_tag;
+  int zm_blocks;
 };
 
 // Arguments of the statistics / controller kernels.

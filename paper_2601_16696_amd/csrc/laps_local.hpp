@@ -651,10 +651,57 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
 // registers and only the preconditioned gradient sigma*g is kept; on
 // rejection nothing is written, so x and log p keep their starting values.
 // ---------------------------------------------------------------------------
+//
+// As for the unadjusted step, workgroups appended to the launch (zm_blocks,
+// FP64 one-oct-per-lane chains on an otherwise idle chip) compute the normals
+// of the next transition (it starts n_traj steps later): row 0 the full
+// refresh, rows 1 + 2j and 2 + 2j the two partial refreshes of integrator
+// step j.  The chain workgroups of that transition load them one step ahead
+// of their use when the slot is tagged with their start step, and compute
+// them as before otherwise; both give the same values.
+template <class Real>
+__device__ void fill_transition_noise(const LocalArgs &a, uint64_t tn, int64_t wb) {
+  const int KR = 2 * a.n_traj + 1;
+  const int64_t octs = (a.d + 7) / 8, per = a.N * octs, total = (int64_t)KR * per;
+  const uint64_t slot = (tn / (uint64_t)a.n_traj) & 1;
+  const int64_t stride = (int64_t)a.zm_blocks * blockDim.x;
+  int64_t idx = wb * blockDim.x + threadIdx.x;
+  if (idx == 0) a.zm_tag[slot] = tn + 1;
+  Real *base = static_cast<Real *>(a.zm) + (size_t)slot * KR * a.N * a.ld;
+  for (; idx < total; idx += stride) {
+    const int rr = (int)(idx / per);
+    const int64_t rem = idx - rr * per, m = rem / octs, oct = rem - m * octs;
+    const uint32_t tag = rr == 0 ? TAG_FULL_REFRESH : ((rr & 1) ? TAG_O_FIRST : TAG_O_SECOND);
+    const uint32_t sub = rr == 0 ? 0u : (uint32_t)((rr - 1) / 2);
+    Real z[8];
+    oct_normals<Real>(a.seed, (uint64_t)m, oct, a.d, tn, tag, sub, z);
+    st8<Real>(base + ((int64_t)rr * a.N + m) * a.ld + 8 * oct, z);
+  }
+}
+
+// Row rr of a transition's normals for oct `oct` of chain m from slot zs.
+template <class Real>
+__device__ __forceinline__ void load_transition_normals(const LocalArgs &a, const Real *zs, bool act, int rr,
+                                                        int64_t m, int64_t oct, Real (&z)[8]) {
+  if (act && 8 * oct < a.d) {
+    ld8<Real>(zs + ((int64_t)rr * a.N + m) * a.ld + 8 * oct, z);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = Real(0);
+  }
+}
+
 template <class Real, int Q, class Tgt, int INTEG>
 __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
   const DevHyper *H = a.hyp;
   if (H->phase != PH_ADJ || H->t >= a.max_total) return;
+  // chain workgroups (the host appends normals workgroups only for one oct per lane)
+  const int cgrid = Q == 1 ? (int)gridDim.x - a.zm_blocks : (int)gridDim.x;
+  if (Q == 1 && (int)blockIdx.x >= cgrid) {
+    const uint64_t tn = (uint64_t)H->t + (uint64_t)a.n_traj;
+    if (tn < (uint64_t)a.max_total) fill_transition_noise<Real>(a, tn, (int64_t)blockIdx.x - cgrid);
+    return;
+  }
   LAPS_TEAM_PROLOGUE(true)
   const double eps = H->eps;
   const uint64_t t = (uint64_t)H->t;
@@ -665,6 +712,13 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
   const Coeffs C = integrator_coeffs(INTEG);
   Tgt tgt;
   Real *X = static_cast<Real *>(a.x);
+  // this transition's normals, when the previous launch wrote them (one oct per lane only: holding the
+  // next step's normals across the gradient stages needs 2 x 8 Q more registers)
+  const int KR = 2 * a.n_traj + 1;
+  const uint64_t zslot = a.n_traj > 0 ? (t / (uint64_t)a.n_traj) & 1 : 0;
+  const Real *zs = (Q == 1 && a.zm_blocks > 0 && a.zm_tag[zslot] == t + 1)
+                       ? static_cast<const Real *>(a.zm) + (size_t)zslot * KR * N * ld
+                       : nullptr;
   // sigma * v for the lane's octs, sigma read from LDS
   auto precond = [&](Real (&v)[Q][8]) {
 #pragma unroll
@@ -678,17 +732,25 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
       }
     }
   };
-  for (int64_t base = (int64_t)blockIdx.x * a.tpw; base < N; base += (int64_t)gridDim.x * a.tpw) {
+  for (int64_t base = (int64_t)blockIdx.x * a.tpw; base < N; base += (int64_t)cgrid * a.tpw) {
     const int64_t m = base + team;
     const bool act = m < N;
     Real x[Q][8], u[Q][8], g[Q][8];
+    Real zf[Q][8];  // loaded normals of the next first partial refresh
     load_row<Real, Q>(X + m * ld, r, T, d, act, x);
+    if (zs) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        load_transition_normals<Real>(a, zs, act, 0, m, r + q * T, u[q]);
+        load_transition_normals<Real>(a, zs, act, 1, m, r + q * T, zf[q]);
+      }
+    }
     double lp = tgt.eval(a, x, g, tm, caux, stage);
     precond(g);
     double v2[2] = {lp, 0.0};
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      oct_normals<Real>(a.seed, (uint64_t)m, r + q * T, d, t, TAG_FULL_REFRESH, 0, u[q]);
+      if (!zs) oct_normals<Real>(a.seed, (uint64_t)m, r + q * T, d, t, TAG_FULL_REFRESH, 0, u[q]);
       Real p = Real(0);
 #pragma unroll
       for (int i = 0; i < 8; ++i) p += u[q][i] * u[q][i];
@@ -705,11 +767,23 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
     }
     double D = 0.0;
     for (int j = 0; j < a.n_traj; ++j) {
+      // loaded path: this step's second-refresh normals are requested now and used after the
+      // gradient stages; the next step's first-refresh normals once this step's are used
+      Real zsec[Q][8];
+      if (zs) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) load_transition_normals<Real>(a, zs, act, 2 + 2 * j, m, r + q * T, zsec[q]);
+      }
       double v3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         Real z[8];
-        oct_normals<Real>(a.seed, (uint64_t)m, r + q * T, d, t, TAG_O_FIRST, (uint32_t)j, z);
+        if (zs) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) z[i] = zf[q][i];
+        } else {
+          oct_normals<Real>(a.seed, (uint64_t)m, r + q * T, d, t, TAG_O_FIRST, (uint32_t)j, z);
+        }
         Real p1 = Real(0), p2 = Real(0), p3 = Real(0);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -723,6 +797,10 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
         v3[1] += widen(p2);
         v3[2] += widen(p3);
         oct_fence();
+      }
+      if (zs && j + 1 < a.n_traj) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) load_transition_normals<Real>(a, zs, act, 3 + 2 * j, m, r + q * T, zf[q]);
       }
       team_sum<3>(v3, T, tm.red, tm.slot);
       const double inw = refresh_scale(a.dyn, v3[0]);
@@ -778,7 +856,12 @@ __global__ void __launch_bounds__(512) k_mams(LocalArgs a) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         Real z[8];
-        oct_normals<Real>(a.seed, (uint64_t)m, r + q * T, d, t, TAG_O_SECOND, (uint32_t)j, z);
+        if (zs) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) z[i] = zsec[q][i];
+        } else {
+          oct_normals<Real>(a.seed, (uint64_t)m, r + q * T, d, t, TAG_O_SECOND, (uint32_t)j, z);
+        }
         Real p = Real(0);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
