@@ -217,8 +217,11 @@ laps_status laps_init(const laps_config *cfg, const laps_target *target, void *x
  * initialisation with the workspace taken from a static device array of the
  * library, 32 MiB per device, held until the process ends (enough for the
  * 4096-chain logistic-regression workload, 23.6 MiB).  Calls no allocating
- * routine.  Configurations whose laps_workspace_size exceeds 32 MiB return
- * LAPS_EWORKSPACE.  The context is library storage, one per device:
+ * routine.  When laps_workspace_size exceeds 32 MiB only because of the
+ * buffers of random normals computed ahead (FP64 per-chain targets with few
+ * chains), the context is created without them and its kernels compute the
+ * normals where they use them (the same values); configurations that exceed
+ * 32 MiB without those buffers return LAPS_EWORKSPACE.  The context is library storage, one per device:
  * laps_destroy leaves it in place, and a later laps_init_static on the same
  * device reuses the array and the context, so the earlier static context is
  * then invalid.  Steps of two static contexts cannot overlap on one device

@@ -88,6 +88,7 @@ struct Shape {
   int T, Q, tpw, block, G, nb, grid_full;
   bool split;
   size_t shmem, shmem_sig;  // dynamic LDS without / with the preconditioner row
+  bool ahead = true;        // normals computed ahead where the shape allows it (noise_blocks)
 };
 
 // Largest dimension of the targets run by the per-chain update kernels
@@ -213,7 +214,7 @@ struct Layout {
 // the chain workgroups occupy at most half of the 1024 SIMDs, so that the
 // appended ones run on compute units that would otherwise idle.
 int noise_blocks(const laps_config *cfg, const laps_target *tg, const Shape &s) {
-  if (!is_local(tg->kind) || cfg->prec != LAPS_F64) return 0;
+  if (!s.ahead || !is_local(tg->kind) || cfg->prec != LAPS_F64) return 0;
   const int64_t grid = s.split ? s.grid_full : s.G;
   if (grid * ((s.block + 63) / 64) > 512) return 0;
   const int64_t items = 2 * cfg->n_chains * ((cfg->d + 7) / 8);  // one thread per oct and refresh
@@ -777,6 +778,12 @@ extern "C" laps_status laps_init_static(const laps_config *cfg, const laps_targe
   Layout L;
   laps_status st = check_init(cfg, tg, x_dev, u0_dev, out, s, L);
   if (st != LAPS_OK) return st;
+  if (L.total > kStaticWorkspaceBytes) {
+    // the buffers of normals computed ahead are an optimisation: without them the kernels compute the
+    // normals where they use them
+    s.ahead = false;
+    L = layout(cfg, tg, s);
+  }
   if (L.total > kStaticWorkspaceBytes) {
     g_last_global = "the configuration needs " + std::to_string(L.total) + " workspace bytes; the static workspace of "
                     "laps_init_static holds " + std::to_string(kStaticWorkspaceBytes);

@@ -56,6 +56,31 @@ def test_static_workspace_matches_caller_workspace(gpu):
         del s, ref
 
 
+def test_static_workspace_without_normals_ahead_matches_caller_workspace(gpu):
+    """An FP64 configuration of the C1 size (1024 chains, d = 100) needs about
+    59 MB with the buffers of normals computed ahead, more than the 32 MiB
+    static array; laps_init_static then drops those buffers and its kernels
+    compute the normals where they use them.  The caller-workspace run keeps
+    them, so the comparison also checks that both ways of getting the normals
+    give the same run bit for bit."""
+    import torch
+    w = workloads.gaussian(n_chains=1024, d=100)
+    cfg = dict(switch_policy=1, max_steps_unadj=30, max_steps_total=30 + 15 * 3)
+    ref = gpu.Sampler(w, "f64", **cfg)
+    assert ref.ws.numel() * ref.ws.element_size() > 32 << 20
+    st_ref, x_ref = _run(ref, 30, 3)
+    s = gpu.Sampler(w, "f64", static_workspace=True, **cfg)
+    assert s.ws is None
+    st, x = _run(s, 30, 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(x, x_ref), np.max(np.abs(x - x_ref))
+    for a, b in zip(st, st_ref):
+        for key in ("t", "grads_per_chain", "phase", "eps", "L", "dtilde", "eevpd", "acc_mean", "n_nonfinite"):
+            assert a[key] == b[key], (key, a[key], b[key])
+    assert st[-1]["phase"] == 2 and st[-1]["n_nonfinite"] == 0
+    del s, ref
+
+
 def test_static_workspace_refuses_oversized_configurations(gpu):
     w = workloads.stochvol(n_chains=4096)
     with pytest.raises(gpu.LapsError, match="static workspace"):
