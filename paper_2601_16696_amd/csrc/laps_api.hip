@@ -139,7 +139,7 @@ bool local_shape(int kind, bool dbl, int64_t N, int64_t d, int team_lanes, Shape
   auto body = [&](int64_t blk) -> size_t {
     size_t b = stage ? (size_t)(blk / T) * ld * rs : 0;
     if (!s.split && blk > T) {
-      const size_t pb = (size_t)4 * 8 * Q * T * 8;  // staging of the per-dim partial row
+      const size_t pb = partials_lds_bytes((int)blk, (int)T, (int)Q);  // staging of the per-dim partial row
       if (pb > b) b = pb;
     }
     return b;
@@ -185,7 +185,7 @@ bool shape_for(const laps_config *cfg, const laps_target *tg, Shape &s) {
     s.G = (int)((cfg->n_chains + s.tpw - 1) / s.tpw);
     s.grid_full = s.G;
     s.split = false;
-    s.shmem = 2 * kRedSlots * sizeof(double) + (size_t)4 * 8 * T * s.Q * 8;
+    s.shmem = 2 * kRedSlots * sizeof(double) + partials_lds_bytes(s.block, T, s.Q);
     s.shmem_sig = s.shmem;
     s.nb = (int)((cfg->d + fin_dims(cfg->d) - 1) / fin_dims(cfg->d));
     return true;

@@ -77,6 +77,17 @@ struct CtlArgs {
 };
 
 enum { FIN_INIT = 0, FIN_UNADJ = 1 };
+
+// LDS bytes that write_partials stages a workgroup's per-dimension partial
+// row through: every wavefront group's four rows (8 Q T doubles each) at once
+// when that fits in kPartialsOneRound bytes, else one group's rows, the
+// groups then added one after another.
+constexpr size_t kPartialsOneRound = 16 * 1024;
+__host__ __device__ inline size_t partials_lds_bytes(int block, int T, int Q) {
+  const int groups = block / (T < 64 ? 64 : T);
+  const size_t rows = (size_t)4 * 8 * Q * T * sizeof(double);
+  return groups > 1 && (size_t)groups * rows <= kPartialsOneRound ? (size_t)groups * rows : rows;
+}
 // dimensions per workgroup of the statistics pass (its block count is
 // ceil(d / fin_dims(d)))
 __host__ __device__ inline int fin_dims(int64_t d) { return d <= 1024 ? 8 : 32; }

@@ -45,6 +45,9 @@ void logreg_splits(int64_t n, int64_t N, int prec, int64_t d, int wgs, int &S, i
   S = (NB + bps - 1) / bps;
 }
 
+// The gate's phase word is read at launch but tested only once the launch's
+// first independent loads are issued (before its first store), so that its
+// latency overlaps theirs; a launch gated off waits for those loads and ends.
 __device__ __forceinline__ bool lr_gate(const LogregArgs &a) {
   if (a.gate == 0) return true;
   const DevHyper *H = a.hyp;
@@ -235,7 +238,7 @@ __device__ __forceinline__ void lr_bwd(const bf16x8 *L, int lane, const bf16x8 (
 
 template <int KC, int DT>
 __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pipe(LogregArgs a) {
-  if (!lr_gate(a)) return;
+  const bool go = lr_gate(a);
   constexpr int kThr = 512;
   constexpr int kFrag = 4 * KC * 64;      // 16-byte fragments per 32-row block
   constexpr int kPer = 2 * kFrag / kThr;   // fragments per thread per stage
@@ -317,6 +320,11 @@ __global__ void __launch_bounds__(512, 2) k_lr_grad_bf16_pipe(LogregArgs a) {
       if (blk < b1) lds_dma16(YF + blk * 8 + (tid & 7), buf + 2 * kFrag);
     }
   };
+  // the gate, tested with theta's loads in flight and before any DMA into LDS
+  if (!go) {
+    __builtin_amdgcn_s_waitcnt(0);
+    return;
+  }
   stage(0, B0);
   stage(1, B1);
   bf16x8 thi[2][KC], tlo[2][KC];
@@ -447,7 +455,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <int KS>  // KS = ceil(d / 4) input-dim steps; d <= 128
 __global__ void __launch_bounds__(256) k_lr_grad_f64_mfma(LogregArgs a) {
-  if (!lr_gate(a)) return;
+  const bool go = lr_gate(a);
   constexpr int DT = (4 * KS + 15) / 16;  // output tiles of 16 dims
   extern __shared__ double sm[];         // [2][16][ldl] rows, then [2][16] labels
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -464,6 +472,10 @@ __global__ void __launch_bounds__(256) k_lr_grad_f64_mfma(LogregArgs a) {
   for (int k = 0; k < KS; ++k) {
     const int64_t e = 4 * k + hi;
     th[k] = (m < N && e < d) ? x[m * ld + e] : 0.0;
+  }
+  if (!go) {
+    __builtin_amdgcn_s_waitcnt(0);
+    return;
   }
   f64x4 gacc[DT];
 #pragma unroll
@@ -646,7 +658,14 @@ __device__ __forceinline__ double lr_theta_terms(const LogregArgs &a, const LrOf
 
 template <class Real, int Q>
 __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
-  if (!lr_gate(a)) return;
+  const bool go = lr_gate(a);
+#define LR_GATE_TEST()            \
+  do {                            \
+    if (!go) {                    \
+      __builtin_amdgcn_s_waitcnt(0); \
+      return;                     \
+    }                             \
+  } while (0)
   extern __shared__ double smem[];
   double *red = smem;
   const int T = a.T;
@@ -676,6 +695,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     // log p and gradient at the caller's positions (a.x): split sums plus the prior
     double lps;
     lr_grad_sum<Real, Q>(a, off, m, r, T, act, x, g, lps);
+    LR_GATE_TEST();
     double v[1] = {lr_theta_terms<Real, Q>(a, off, r, T, x)};
     team_sum<1>(v, T, red, slot);
     if (act) {
@@ -695,6 +715,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     }
     double lps;
     lr_grad_sum<Real, Q>(a, off, m, r, T, act, x, g, lps);
+    LR_GATE_TEST();
     if (mode == LR_INIT) {
       lane_normals<Real, Q>(a.seed, (uint64_t)m, r, T, d, 0, TAG_INIT_DIR, 0, z);
       double v[3] = {lr_theta_terms<Real, Q>(a, off, r, T, x), 0.0, 0.0};
@@ -802,6 +823,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
         u[q][i] = A1 * u[q][i] + B1 * g[q][i];
         x[q][i] += epsR * u[q][i];
       }
+    LR_GATE_TEST();
     if (act) {
       store_row<Real, Q>(X + m * ld, r, T, d, x);
       store_row<Real, Q>(U + m * ld, r, T, d, u);
@@ -851,6 +873,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
 
   if (mode == LR_MBEGIN) {
     load_row<Real, Q>(Gc + m * ld, r, T, d, act, g);
+    LR_GATE_TEST();
     if (act) {
       store_row<Real, Q>(X0 + m * ld, r, T, d, x);
       store_row<Real, Q>(G0 + m * ld, r, T, d, g);
@@ -885,6 +908,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   load_row<Real, Q>(U + m * ld, r, T, d, act, u);
   double lps;
   lr_grad_sum<Real, Q>(a, off, m, r, T, act, x, g, lps);
+  LR_GATE_TEST();
   double v[3] = {lr_theta_terms<Real, Q>(a, off, r, T, x), 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < Q; ++q)
@@ -971,6 +995,7 @@ __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
     }
   }
 }
+#undef LR_GATE_TEST
 
 // ---------------------------------------------------------------------------
 hipError_t launch_logreg_pack(const LogregArgs &a, hipStream_t s) {

@@ -142,6 +142,30 @@ __device__ __forceinline__ void write_partials(double *partials, int64_t d, int6
   const int grp = threadIdx.x / (T < 64 ? 64 : T);
   const int lig = threadIdx.x - grp * (T < 64 ? 64 : T);  // lane index inside its group
   const int span = 8 * Q * lanes;
+  if (partials_lds_bytes(blockDim.x, T, Q) > (size_t)4 * span * sizeof(double)) {
+    // every group stages its rows at once (after a barrier: the buffer may
+    // hold other teams' staged rows until then), one barrier, then the
+    // workgroup's threads add the groups in order (0 + group 0 + group 1 + ...,
+    // the order of the loop below); element c of a row is coordinate c of the
+    // chain (c = 8 (q T + lane) + i)
+    __syncthreads();
+    if (lig < lanes) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) buf[(grp * 4 + k) * span + (q * lanes + lig) * 8 + i] = S[k][q][i];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 4 * span; e += blockDim.x) {
+      const int k = e / span, c = e - k * span;
+      double v = 0.0;
+      for (int gI = 0; gI < groups; ++gI) v += buf[(gI * 4 + k) * span + c];
+      if (8 * (c / 8) < d) P[k * ld + c] = v;
+    }
+    return;
+  }
   for (int gI = 0; gI < groups; ++gI) {
     if (grp == gI && lig < lanes) {
 #pragma unroll
