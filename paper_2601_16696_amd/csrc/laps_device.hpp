@@ -113,6 +113,26 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// own + partner for the lane partner l ^ MSK (MSK = 16 or 32) with the gfx950
+// lane swaps instead of an LDS permute: v_permlane16_swap(v, v) gives every
+// lane the value of the even 16-lane row of its pair in the first result and
+// of the odd row in the second (v_permlane32_swap the same for the two 32-lane
+// halves), so first + second is the pair's sum in every lane, equal to
+// own + partner (addition is commutative).
+template <int MSK>
+__device__ __forceinline__ double xor_pair_sum(double v) {
+  static_assert(MSK == 16 || MSK == 32, "row or half swap");
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const auto l = MSK == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, true, false)
+                           : __builtin_amdgcn_permlane32_swap(lo, lo, true, false);
+  const auto h = MSK == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, true, false)
+                           : __builtin_amdgcn_permlane32_swap(hi, hi, true, false);
+  const double e = __longlong_as_double((long long)(((uint64_t)h[0] << 32) | l[0]));
+  const double o = __longlong_as_double((long long)(((uint64_t)h[1] << 32) | l[1]));
+  return e + o;
+}
+
 // Sum over each aligned group of T lanes (T a power of two up to 64), the same
 // value in every lane of a group.  Masks of 16 and 32 are xor shuffles; below
 // 16 the partners are the DPP row mirror (i <-> 15 - i), the half-row mirror
@@ -121,9 +141,13 @@ __device__ __forceinline__ double dpp_f64(double v) {
 // is added as (own + partner), so both partners hold identical sums.
 template <int NV>
 __device__ __forceinline__ void group_sum(double (&v)[NV], int T) {
-  for (int msk = T >> 1; msk >= 16; msk >>= 1) {
+  if (T >= 64) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], msk);
+    for (int k = 0; k < NV; ++k) v[k] = xor_pair_sum<32>(v[k]);
+  }
+  if (T >= 32) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = xor_pair_sum<16>(v[k]);
   }
   if (T >= 16) {
 #pragma unroll

@@ -127,14 +127,31 @@ __device__ __forceinline__ void write_partials(double *partials, int64_t d, int6
       }
     return;
   }
-  // T < blockDim: first fold teams that share a wavefront
-  for (int msk = T; msk < 64; msk <<= 1) {
+  // T < blockDim: first fold teams that share a wavefront (xor butterflies;
+  // the levels of 16 and 32 lanes by lane swaps)
+  for (int msk = T; msk < 16; msk <<= 1) {
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int i = 0; i < 8; ++i) S[k][q][i] += __shfl_xor(S[k][q][i], msk);
+  }
+  if (T <= 16) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) S[k][q][i] = xor_pair_sum<16>(S[k][q][i]);
+  }
+  if (T <= 32) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) S[k][q][i] = xor_pair_sum<32>(S[k][q][i]);
   }
   // then wavefront (or multi-wave team) groups in order, accumulated in LDS
   const int lanes = T;  // lanes holding a distinct set of dims
