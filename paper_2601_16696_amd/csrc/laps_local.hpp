@@ -391,7 +391,7 @@ __device__ __forceinline__ void stage_row(Real *dst, const void *src, int64_t ld
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) t[i] = s[i];
 }
 
-#define LAPS_TEAM_PROLOGUE(WITH_SIGMA)                                                              \
+#define LAPS_TEAM_DECLS(WITH_SIGMA)                                                                 \
   extern __shared__ double smem[];                                                                  \
   const int T = a.T;                                                                                \
   const int team = threadIdx.x / T, r = threadIdx.x - team * T;                                     \
@@ -401,7 +401,9 @@ __device__ __forceinline__ void stage_row(Real *dst, const void *src, int64_t ld
   Real *caux = reinterpret_cast<Real *>(smem + 2 * kRedSlots);                                      \
   Real *csig = caux + (Tgt::kAux ? ld : 0);                                                         \
   Real *body = csig + ((WITH_SIGMA) ? ld : 0);                                                      \
-  Real *stage = Tgt::stage(T) ? body + (size_t)team * ld : nullptr;                                 \
+  Real *stage = Tgt::stage(T) ? body + (size_t)team * ld : nullptr;
+
+#define LAPS_TEAM_STAGE(WITH_SIGMA)                                                                 \
   if (Tgt::kAux) {                                                                                  \
     if (a.aux)                                                                                      \
       stage_row<Real>(caux, a.aux, ld);                                                             \
@@ -410,6 +412,10 @@ __device__ __forceinline__ void stage_row(Real *dst, const void *src, int64_t ld
   }                                                                                                 \
   if (WITH_SIGMA) stage_row<Real>(csig, a.sigma, ld);                                               \
   if (Tgt::kAux || (WITH_SIGMA)) __syncthreads();
+
+#define LAPS_TEAM_PROLOGUE(WITH_SIGMA) \
+  LAPS_TEAM_DECLS(WITH_SIGMA)          \
+  LAPS_TEAM_STAGE(WITH_SIGMA)
 
 // ---------------------------------------------------------------------------
 // Initialisation: log p and gradient at x, u = g/|g| (u0 if given; a uniform
@@ -523,17 +529,29 @@ __device__ __forceinline__ void step_normals(const LocalArgs &a, const Real *zs,
 
 template <class Real, int Q, class Tgt, bool STATS>
 __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
+  // The phase word, the step's scalars, both normal slots' tags and the
+  // launch's first independent loads (the shift row, the staged aux row) are
+  // issued together; the phase is tested after the staging barrier (uniformly)
+  // and before the first global store, so no load waits for another.
   const DevHyper *H = a.hyp;
-  if (H->phase != PH_UNADJ) return;
-  const int cgrid = (int)gridDim.x - a.zn_blocks;  // chain workgroups
-  if ((int)blockIdx.x >= cgrid) {
-    fill_step_noise<Real>(a, (uint64_t)H->t + 1, (int64_t)(blockIdx.x - cgrid) * blockDim.x + threadIdx.x);
-    return;
-  }
-  LAPS_TEAM_PROLOGUE(false)
+  const int phase = H->phase;
   const double eps = H->eps, Lm = H->L;
   const uint64_t t = (uint64_t)H->t;
-  const Real *zs = (a.zn_blocks > 0 && a.zn_tag[t & 1] == t + 1)
+  const uint64_t tag0 = a.zn_blocks > 0 ? a.zn_tag[0] : 0, tag1 = a.zn_blocks > 0 ? a.zn_tag[1] : 0;
+  LAPS_TEAM_DECLS(false)
+  double K[STATS ? Q : 1][8];
+  if constexpr (STATS) load_shift<Q>(a.shiftK, r, T, d, K);
+  LAPS_TEAM_STAGE(false)
+  if (phase != PH_UNADJ) {
+    __builtin_amdgcn_s_waitcnt(0);
+    return;
+  }
+  const int cgrid = (int)gridDim.x - a.zn_blocks;  // chain workgroups
+  if ((int)blockIdx.x >= cgrid) {
+    fill_step_noise<Real>(a, t + 1, (int64_t)(blockIdx.x - cgrid) * blockDim.x + threadIdx.x);
+    return;
+  }
+  const Real *zs = (a.zn_blocks > 0 && ((t & 1) ? tag1 : tag0) == t + 1)
                        ? static_cast<const Real *>(a.zn) + (size_t)(t & 1) * 2 * N * ld
                        : nullptr;
   const double h = 0.5 * eps;
@@ -541,8 +559,6 @@ __global__ void __launch_bounds__(512) k_unadj(LocalArgs a) {
   const Real c1 = (Real)c1d, c2 = (Real)c2d, epsR = (Real)eps;
   Tgt tgt;
   double S[4][STATS ? Q : 1][8] = {};
-  double K[STATS ? Q : 1][8];
-  if constexpr (STATS) load_shift<Q>(a.shiftK, r, T, d, K);
   const bool keep_g = Tgt::kCache || a.cache;
   Real *X = static_cast<Real *>(a.x);
   Real *U = static_cast<Real *>(a.u);
