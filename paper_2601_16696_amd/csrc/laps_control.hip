@@ -100,20 +100,63 @@ __device__ void ctl_unadj_body(const CtlArgs &c, double *sh, double &mean_sh) {
   double s = 0.0, q = 0.0, nb = 0.0;
   const int64_t B = blockDim.x, N = c.N;
   int64_t m = threadIdx.x;
+  // The thread's first kPre energy errors (m, m + B, ...) and its first block
+  // scalars are loaded at once (clamped indices, values past the end unused);
+  // the sums below take them in the order of the plain strided loops: groups
+  // of four while a whole group remains, then single values.
+  constexpr int kPre = 16;
+  double pv[kPre];
+#pragma unroll
+  for (int j = 0; j < kPre; ++j) {
+    const int64_t idx = m + j * B;
+    pv[j] = c.delta[idx < N ? idx : N - 1];
+  }
+  const int bf = (int)threadIdx.x < c.nb ? (int)threadIdx.x : c.nb - 1;
+  const double pf0 = c.part2[bf * 4 + 0], pf1 = c.part2[bf * 4 + 1], pf2 = c.part2[bf * 4 + 2];
+  int j = 0;  // index of m's value among the thread's
+#pragma unroll
+  for (int g = 0; g < kPre / 4; ++g) {
+    if (m + 3 * B < N) {
+      const double a0 = pv[4 * g], a1 = pv[4 * g + 1], a2 = pv[4 * g + 2], a3 = pv[4 * g + 3];
+      s += (a0 + a1) + (a2 + a3);
+      q += (a0 * a0 + a1 * a1) + (a2 * a2 + a3 * a3);
+      nb += (double)(!isfinite(a0)) + (double)(!isfinite(a1)) + (double)(!isfinite(a2)) + (double)(!isfinite(a3));
+      m += 4 * B;
+      j += 4;
+    }
+  }
   for (; m + 3 * B < N; m += 4 * B) {
     const double a0 = c.delta[m], a1 = c.delta[m + B], a2 = c.delta[m + 2 * B], a3 = c.delta[m + 3 * B];
     s += (a0 + a1) + (a2 + a3);
     q += (a0 * a0 + a1 * a1) + (a2 * a2 + a3 * a3);
     nb += (double)(!isfinite(a0)) + (double)(!isfinite(a1)) + (double)(!isfinite(a2)) + (double)(!isfinite(a3));
+    j += 4;
   }
-  for (; m < N; m += B) {
-    const double v = c.delta[m];
-    s += v;
-    q += v * v;
-    if (!isfinite(v)) nb += 1.0;
+  // at most three values remain (m + 3 B >= N)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (m < N) {
+      double v = 0.0;
+      if (j < kPre) {
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) v = (i == j) ? pv[i] : v;
+      } else {
+        v = c.delta[m];
+      }
+      s += v;
+      q += v * v;
+      if (!isfinite(v)) nb += 1.0;
+      m += B;
+      ++j;
+    }
   }
   double p3[3] = {0.0, 0.0, -INFINITY};
-  for (int b = threadIdx.x; b < c.nb; b += blockDim.x) {
+  if ((int)threadIdx.x < c.nb) {
+    p3[0] += pf0;
+    p3[1] += pf1;
+    p3[2] = nanmax(p3[2], pf2);
+  }
+  for (int b = threadIdx.x + blockDim.x; b < c.nb; b += blockDim.x) {
     p3[0] += c.part2[b * 4 + 0];
     p3[1] += c.part2[b * 4 + 1];
     p3[2] = nanmax(p3[2], c.part2[b * 4 + 2]);
