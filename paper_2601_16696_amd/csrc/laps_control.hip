@@ -11,17 +11,30 @@
 
 namespace laps {
 
-// Fixed-order block reduction of NV doubles over a 256-thread block; the
-// result is valid in thread 0.  op: 0 sum, 1 NaN-propagating max.
+// Fixed-order block reduction of NV doubles over a block; the result is
+// valid in thread 0.  op: 0 sum, 1 NaN-propagating max.  Inside a wavefront
+// an xor butterfly from 32 lanes down to 1, each lane combining (own,
+// partner): the partners of 32 and 16 through the lane swaps, those of 8, 4,
+// 2, 1 by rotations inside 16-lane rows (a rotation by 16 - K hands lane l the
+// value of lane l + K mod 16, which is l ^ K for every lane whose value
+// reaches lane 0, as bit K of such a lane is clear at level K).
 template <int NV>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV], double *sh) {
 #pragma unroll
-  for (int msk = 32; msk >= 1; msk >>= 1)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      const double o = __shfl_xor(v[k], msk);
-      v[k] = op[k] == 0 ? v[k] + o : nanmax(v[k], o);
-    }
+  for (int k = 0; k < NV; ++k) {
+    double o = xor_partner<32>(v[k]);
+    v[k] = op[k] == 0 ? v[k] + o : nanmax(v[k], o);
+    o = xor_partner<16>(v[k]);
+    v[k] = op[k] == 0 ? v[k] + o : nanmax(v[k], o);
+    o = dpp_f64<0x128>(v[k]);  // row_ror:8
+    v[k] = op[k] == 0 ? v[k] + o : nanmax(v[k], o);
+    o = dpp_f64<0x12C>(v[k]);  // row_ror:12
+    v[k] = op[k] == 0 ? v[k] + o : nanmax(v[k], o);
+    o = dpp_f64<0x12E>(v[k]);  // row_ror:14
+    v[k] = op[k] == 0 ? v[k] + o : nanmax(v[k], o);
+    o = dpp_f64<0x12F>(v[k]);  // row_ror:15
+    v[k] = op[k] == 0 ? v[k] + o : nanmax(v[k], o);
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if (lane == 0)
 #pragma unroll
@@ -220,10 +233,18 @@ __device__ void ctl_unadj_body(const CtlArgs &c, double *sh, double &mean_sh) {
 // reduced the same way over its slots.
 template <int DIMS>
 __device__ __forceinline__ void fin_combine(double (&v)[4], double *sh, int dl, int rg) {
+  // xor levels DIMS .. 32 (own + partner): 8 by a rotation by 8 inside 16-lane
+  // rows (exactly lane l ^ 8), 16 and 32 through the lane swaps
+  if (DIMS <= 8) {
 #pragma unroll
-  for (int msk = DIMS; msk < 64; msk <<= 1)
+    for (int k = 0; k < 4; ++k) v[k] += dpp_f64<0x128>(v[k]);
+  }
+  if (DIMS <= 16) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], msk);
+    for (int k = 0; k < 4; ++k) v[k] = xor_pair_sum<16>(v[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = xor_pair_sum<32>(v[k]);
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if ((threadIdx.x & 63) < DIMS)
 #pragma unroll

@@ -120,7 +120,7 @@ __device__ __forceinline__ double dpp_f64(double v) {
 // halves), so first + second is the pair's sum in every lane, equal to
 // own + partner (addition is commutative).
 template <int MSK>
-__device__ __forceinline__ double xor_pair_sum(double v) {
+__device__ __forceinline__ void xor_pair(double v, double &e, double &o) {
   static_assert(MSK == 16 || MSK == 32, "row or half swap");
   const uint64_t b = (uint64_t)__double_as_longlong(v);
   const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
@@ -128,9 +128,21 @@ __device__ __forceinline__ double xor_pair_sum(double v) {
                            : __builtin_amdgcn_permlane32_swap(lo, lo, true, false);
   const auto h = MSK == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, true, false)
                            : __builtin_amdgcn_permlane32_swap(hi, hi, true, false);
-  const double e = __longlong_as_double((long long)(((uint64_t)h[0] << 32) | l[0]));
-  const double o = __longlong_as_double((long long)(((uint64_t)h[1] << 32) | l[1]));
+  e = __longlong_as_double((long long)(((uint64_t)h[0] << 32) | l[0]));
+  o = __longlong_as_double((long long)(((uint64_t)h[1] << 32) | l[1]));
+}
+template <int MSK>
+__device__ __forceinline__ double xor_pair_sum(double v) {
+  double e, o;
+  xor_pair<MSK>(v, e, o);
   return e + o;
+}
+// The value of lane l ^ MSK itself (lane swaps and a select by the lane's bit).
+template <int MSK>
+__device__ __forceinline__ double xor_partner(double v) {
+  double e, o;
+  xor_pair<MSK>(v, e, o);
+  return (threadIdx.x & MSK) ? e : o;
 }
 
 // Sum over each aligned group of T lanes (T a power of two up to 64), the same
