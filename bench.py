@@ -52,7 +52,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the bf16 gradient kernel on the logistic-regression workload, from FETCH_SIZE
 # and WRITE_SIZE counters scaled by what they read for a plain copy of known size; kept with the counter
 # summary under profiles/ and reset to None whenever the kernel changes.
-LR_GRAD_TRAFFIC_BYTES = 35.08e6
+LR_GRAD_TRAFFIC_BYTES = 35.09e6
 # Instructions per launch of the same kernel (SQ_INSTS_VALU, which includes the MFMA instructions,
 # SQ_INSTS_MFMA and SQ_INSTS_VALU_TRANS_F32, mean per dispatch), kept with the counter summary under
 # profiles/ and reset to None whenever the kernel changes: they give the vector-ALU ceiling reported
@@ -62,8 +62,8 @@ SIMDS, CLOCK_HZ = 1024, 2.4e9  # 256 CUs x 4 SIMDs at 2.4 GHz
 # Vector instructions (SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32) per launch of the per-chain step kernels,
 # from the counter summary under profiles/; reset to None whenever a kernel changes.
 STEP_INSTS = {
-    "stochvol": {"unadj": (30375937, 909313), "mams": (942860609, 27885571)},
-    "phi4": {"unadj": (20598784, 571392), "mams": (552040953, 9981952)},
+    "stochvol": {"unadj": (30373889, 909313), "mams": (945985857, 27885571)},
+    "phi4": {"unadj": (20598784, 571392), "mams": (552036857, 9981952)},
 }
 
 

@@ -153,13 +153,12 @@ __device__ __forceinline__ double xor_partner(double v) {
 // is added as (own + partner), so both partners hold identical sums.
 template <int NV>
 __device__ __forceinline__ void group_sum(double (&v)[NV], int T) {
-  if (T >= 64) {
+  // (the lane swaps of xor_pair_sum in place of these two levels changed the
+  // FP64 stochastic-volatility runs, teams of 192 lanes, at the bit level; not
+  // used here)
+  for (int msk = T >> 1; msk >= 16; msk >>= 1) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = xor_pair_sum<32>(v[k]);
-  }
-  if (T >= 32) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = xor_pair_sum<16>(v[k]);
+    for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], msk);
   }
   if (T >= 16) {
 #pragma unroll
