@@ -153,9 +153,10 @@ __device__ __forceinline__ double xor_partner(double v) {
 // is added as (own + partner), so both partners hold identical sums.
 template <int NV>
 __device__ __forceinline__ void group_sum(double (&v)[NV], int T) {
-  // (the lane swaps of xor_pair_sum in place of these two levels changed the
-  // FP64 stochastic-volatility runs, teams of 192 lanes, at the bit level; not
-  // used here)
+  // (xor_pair_sum's lane swaps give these two levels the same sums, but in the
+  // FP64 stochastic-volatility step kernel the compiler then contracted one
+  // multiply-add elsewhere differently, so those runs changed at the bit
+  // level; kept as shuffles)
   for (int msk = T >> 1; msk >= 16; msk >>= 1) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], msk);
