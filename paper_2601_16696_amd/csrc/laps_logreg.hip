@@ -659,12 +659,12 @@ __device__ __forceinline__ double lr_theta_terms(const LogregArgs &a, const LrOf
 template <class Real, int Q>
 __global__ void __launch_bounds__(256) k_lr_update(LogregArgs a) {
   const bool go = lr_gate(a);
-#define LR_GATE_TEST()            \
-  do {                            \
-    if (!go) {                    \
+#define LR_GATE_TEST()               \
+  do {                               \
+    if (!go) {                       \
       __builtin_amdgcn_s_waitcnt(0); \
-      return;                     \
-    }                             \
+      return;                        \
+    }                                \
   } while (0)
   extern __shared__ double smem[];
   double *red = smem;
