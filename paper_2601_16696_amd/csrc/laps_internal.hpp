@@ -78,15 +78,26 @@ struct CtlArgs {
 
 enum { FIN_INIT = 0, FIN_UNADJ = 1 };
 
-// LDS bytes that write_partials stages a workgroup's per-dimension partial
-// row through: every wavefront group's four rows (8 Q T doubles each) at once
-// when that fits in kPartialsOneRound bytes, else one group's rows, the
-// groups then added one after another.
-constexpr size_t kPartialsOneRound = 16 * 1024;
+// How write_partials stages a workgroup's per-dimension partial row through
+// LDS (the four rows of a group hold 8 Q T doubles each):
+//   2: teams of at most 32 lanes, every 32-lane half of every wavefront at once
+//      (folded over its 16-lane rows only), within kPartialsHalves bytes;
+//   1: every wavefront group's folded rows at once, within kPartialsOneRound;
+//   0: one group's rows, the groups then added one after another.
+constexpr size_t kPartialsOneRound = 16 * 1024, kPartialsHalves = 32 * 1024;
+__host__ __device__ inline int partials_mode(int block, int T, int Q) {
+  const int groups = block / (T < 64 ? 64 : T);
+  const size_t rows = (size_t)4 * 8 * Q * T * sizeof(double);
+  if (T <= 32 && (size_t)2 * groups * rows <= kPartialsHalves) return 2;
+  if (groups > 1 && (size_t)groups * rows <= kPartialsOneRound) return 1;
+  return 0;
+}
+// The LDS bytes of that staging.
 __host__ __device__ inline size_t partials_lds_bytes(int block, int T, int Q) {
   const int groups = block / (T < 64 ? 64 : T);
   const size_t rows = (size_t)4 * 8 * Q * T * sizeof(double);
-  return groups > 1 && (size_t)groups * rows <= kPartialsOneRound ? (size_t)groups * rows : rows;
+  const int mode = partials_mode(block, T, Q);
+  return mode == 2 ? (size_t)2 * groups * rows : mode == 1 ? (size_t)groups * rows : rows;
 }
 // dimensions per workgroup of the statistics pass (its block count is
 // ceil(d / fin_dims(d)))

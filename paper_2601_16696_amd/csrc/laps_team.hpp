@@ -128,7 +128,9 @@ __device__ __forceinline__ void write_partials(double *partials, int64_t d, int6
     return;
   }
   // T < blockDim: first fold teams that share a wavefront (xor butterflies;
-  // the levels of 16 and 32 lanes by lane swaps)
+  // the levels of 16 and 32 lanes by lane swaps; in mode 2 the level of 32 is
+  // left to the reader, which adds the two halves first, as that level would)
+  const int mode = partials_mode(blockDim.x, T, Q);
   for (int msk = T; msk < 16; msk <<= 1) {
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -145,7 +147,7 @@ __device__ __forceinline__ void write_partials(double *partials, int64_t d, int6
 #pragma unroll
         for (int i = 0; i < 8; ++i) S[k][q][i] = xor_pair_sum<16>(S[k][q][i]);
   }
-  if (T <= 32) {
+  if (T <= 32 && mode != 2) {
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -159,7 +161,33 @@ __device__ __forceinline__ void write_partials(double *partials, int64_t d, int6
   const int grp = threadIdx.x / (T < 64 ? 64 : T);
   const int lig = threadIdx.x - grp * (T < 64 ? 64 : T);  // lane index inside its group
   const int span = 8 * Q * lanes;
-  if (partials_lds_bytes(blockDim.x, T, Q) > (size_t)4 * span * sizeof(double)) {
+  if (mode == 2) {
+    // half hg of wavefront grp stages its rows as group 2 grp + hg (its lane
+    // index lh is the team lane: after the folds below 32 lanes its first T
+    // lanes hold the half's sums); the reader adds half 0 + half 1 of each
+    // wavefront, then the wavefronts in order from 0
+    const int hg = (threadIdx.x >> 5) & 1, lh = threadIdx.x & 31;
+    __syncthreads();  // the buffer may hold other teams' staged rows until here
+    if (lh < lanes) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            buf[((2 * grp + hg) * 4 + k) * span + (q * lanes + lh) * 8 + i] = S[k][q][i];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 4 * span; e += blockDim.x) {
+      const int k = e / span, c = e - k * span;
+      double v = 0.0;
+      for (int gI = 0; gI < groups; ++gI)
+        v += buf[((2 * gI) * 4 + k) * span + c] + buf[((2 * gI + 1) * 4 + k) * span + c];
+      if (8 * (c / 8) < d) P[k * ld + c] = v;
+    }
+    return;
+  }
+  if (mode == 1) {
     // every group stages its rows at once (after a barrier: the buffer may
     // hold other teams' staged rows until then), one barrier, then the
     // workgroup's threads add the groups in order (0 + group 0 + group 1 + ...,
